@@ -1,0 +1,181 @@
+/*
+ * sap.h -- C ABI of the MI355X (gfx950) Secant-Avoidance Projection library.
+ *
+ * The method (Kvinge, Farnell, Kirby, Peterson, "A GPU-Oriented Algorithm
+ * Design for Secant-Based Dimensionality Reduction", 2018, Sec. 4 and
+ * Algorithm 1) looks for an n x k projection P with orthonormal columns that
+ * maximises the smallest projected unit-secant norm
+ *         r_ij = || P^T (x_i - x_j) || / || x_i - x_j ||     (i < j)
+ * over a point cloud X (N x n).  One iteration evaluates every r_ij, reduces
+ * to the global minimum and its pair, and rotates span(P) toward that worst
+ * secant (argmax basis vector, modified Gram-Schmidt, alpha shift).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers on the handle's device unless
+ *    stated otherwise; result structs are HOST memory.
+ *  - X is N x n row-major with leading dimension ldx >= n (elements), FP64
+ *    or FP32.  X is BORROWED: the caller keeps it alive and unchanged until
+ *    sap_destroy.  Every other buffer is owned by the library.
+ *  - P arguments are n x k row-major, contiguous (element (l, c) at l*k + c).
+ *  - Pairs are unordered, i < j, indexed q = i*N - i*(i+1)/2 + (j - i - 1).
+ *    Argmin ties are broken by the smallest (i, j).
+ *  - Work is enqueued on the stream given to sap_init (or sap_set_stream).
+ *    Only sap_min_secant, sap_step with a non-NULL result, sap_info and
+ *    sap_softmin_stats synchronise that stream.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *  - Errors are returned as status codes, never thrown.  SAP_ERR_DEVICE
+ *    poisons the handle: afterwards only sap_last_error and sap_destroy work.
+ *
+ * Two forms of the per-iteration pass are provided:
+ *  - SAP_PLAIN stores every unit secant once (n x p, component-major, the
+ *    paper's "secants as columns of S", Sec. 4) in the dtype of X and streams
+ *    it from HBM each iteration;
+ *  - SAP_FUSED never stores a secant: it forms Y = (X - mean) P on the
+ *    matrix cores in FP64, rounds Y to FP32, and scores (i, j) tiles as
+ *    ||y_i - y_j||^2 * (1/d_ij^2) with the denominators precomputed once.
+ * Both forms rescore, in FP64 from X, every pair whose coarse value lies in a
+ * window proven (from the rounding-error bound of the coarse pass) to
+ * contain the true minimum, so the reported minimum and pair are those of
+ * an FP64 evaluation.  The fused form evaluates pairs shorter than a cutoff
+ * D_c directly in FP64 every iteration, because there the coarse error,
+ * which grows like 1/d, would swamp them.
+ */
+#ifndef SAP_H
+#define SAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sap_ctx *sap_handle;
+
+typedef enum {
+    SAP_OK = 0,
+    SAP_ERR_INVALID_ARG = 1,      /* bad size, range, pointer or combination      */
+    SAP_ERR_NONFINITE = 2,        /* NaN or Inf in X or P                          */
+    SAP_ERR_NO_PAIRS = 3,         /* every pair is a duplicate or shorter than l   */
+    SAP_ERR_OUT_OF_MEMORY = 4,    /* device allocation failed                      */
+    SAP_ERR_DEVICE = 5,           /* HIP runtime error; the handle is poisoned     */
+    SAP_ERR_NOT_ORTHONORMAL = 6,  /* max |P^T P - I| > 1e-6                        */
+    SAP_ERR_POISONED = 7,         /* handle unusable after an earlier device error */
+    SAP_ERR_UNSUPPORTED = 8,      /* valid request outside this build's limits     */
+    SAP_ERR_CAPACITY = 9          /* a library-owned list would exceed its cap     */
+} sap_status;
+
+enum { SAP_F64 = 0, SAP_F32 = 1 };                       /* dtype of X           */
+enum { SAP_PLAIN = 0, SAP_FUSED = 1 };                   /* form of the pass     */
+enum { SAP_STEP_LITERAL = 0, SAP_STEP_NORMALIZED = 1 };  /* reading of the shift */
+
+/* Configuration (Algorithm 1's inputs: target dimension k, shift alpha; the
+ * length threshold l of Sec. 7).
+ *   N >= 2, 1 <= k <= min(n, 16), n*(k+3) <= 19200 (the FP64 update keeps its
+ *   vectors in LDS), alpha in [0, 1], min_len >= 0.
+ *   rule: SAP_STEP_LITERAL combines the unnormalised P P^T s and s - P P^T s
+ *         (the paper's wording); SAP_STEP_NORMALIZED combines their unit
+ *         vectors.
+ *   close_d: fused form only; pairs with d < close_d are evaluated in FP64
+ *         every iteration.  < 0 selects it automatically from the coarse
+ *         error bound (see sap_info).  close_cap bounds that list (0 = 1<<20);
+ *         an automatic cutoff is lowered until the list fits, an explicit one
+ *         that does not fit fails with SAP_ERR_CAPACITY. */
+typedef struct {
+    int64_t N;
+    int32_t n, k;
+    int32_t dtype;      /* SAP_F64 | SAP_F32                        */
+    int32_t form;       /* SAP_PLAIN | SAP_FUSED                    */
+    int32_t rule;       /* SAP_STEP_LITERAL | SAP_STEP_NORMALIZED   */
+    int32_t close_cap;
+    double alpha;
+    double min_len;
+    double close_d;
+} sap_config;
+
+/* One evaluation of the secant set (Algorithm 1, the argmin step). */
+typedef struct {
+    double min_norm;     /* FP64 min of ||P^T s|| over kept pairs              */
+    int64_t i, j;        /* its pair (i < j), smallest (i, j) on ties            */
+    int64_t pair_index;  /* q(i, j)                                            */
+    double coarse_min;   /* smallest coarse (FP32/FP64-pass) value; -1 if none */
+    double window;       /* coarse values within this of coarse_min were rescored */
+    int32_t certified;   /* 1: the pair is provably the FP64 argmin            */
+    int32_t n_rescored;  /* pairs evaluated in FP64 this iteration             */
+    int32_t t;           /* basis vector replaced by the update (0-based)      */
+    int32_t reserved;
+} sap_min_result;
+
+/* Sizes and precision parameters of a handle (host struct). */
+typedef struct {
+    int64_t n_pairs;        /* kept pairs |Pi|                                  */
+    int64_t n_dropped;      /* duplicates + pairs shorter than min_len          */
+    int64_t n_close;        /* fused: pairs evaluated in FP64 every iteration    */
+    double close_d;         /* fused: cutoff D_c actually used                   */
+    double e_abs, e_rel;    /* coarse error bound |r~ - r| <= e_abs + e_rel r    */
+    double radius;          /* max_i ||x_i - mean||                             */
+    int64_t bytes_per_iter; /* algorithmic HBM bytes of one pair pass            */
+    int64_t device_bytes;   /* device memory owned by the handle                */
+    int64_t n_tiles;        /* tiles (fused) or chunks (plain) of the pair pass  */
+} sap_info_t;
+
+/* Create a handle: validate, allocate, check X is finite and P0 orthonormal,
+ * and precompute the secant array (plain) or the tile-packed 1/d^2 array and
+ * the short-pair list (fused).  P0 is n x k FP64.  stream is a hipStream_t
+ * (NULL = the null stream).  On failure *out is NULL. */
+sap_status sap_init(const sap_config *cfg, const void *X, int64_t ldx,
+                    const double *P0, void *stream, sap_handle *out);
+
+/* Evaluate the current P: min, argmin and the rescoring record.  Synchronises. */
+sap_status sap_min_secant(sap_handle h, sap_min_result *out);
+
+/* One iteration: evaluate, then apply the update to P.  With out == NULL it
+ * is fully asynchronous; otherwise it synchronises and reports the
+ * evaluation that drove the update. */
+sap_status sap_step(sap_handle h, sap_min_result *out_or_null);
+
+/* Algorithm 1 from the current P: iters updates and iters+1 evaluations (the
+ * last one scores the returned P).  Traces are device buffers of iters+1
+ * entries: min (FP64), (i, j) as 2 int64 per entry, certified (int32).
+ * ij_trace and cert_trace may be NULL.  Asynchronous. */
+sap_status sap_run(sap_handle h, int32_t iters, double *min_trace,
+                   int64_t *ij_trace, int32_t *cert_trace);
+
+/* Copy the FP64 master P out (n x k row-major device buffer) / replace it.
+ * sap_set_P checks orthonormality (max |P^T P - I| <= 1e-6) and synchronises. */
+sap_status sap_get_P(sap_handle h, double *P_out);
+sap_status sap_set_P(sap_handle h, const double *P);
+
+/* Change the stream later work is enqueued on. */
+sap_status sap_set_stream(sap_handle h, void *stream);
+
+/* Sizes and error-bound parameters.  Synchronises. */
+sap_status sap_info(sap_handle h, sap_info_t *out);
+
+/* Soft-min surrogate of the minimum (not in the paper; fused form only):
+ *   L = -tau log sum_{kept i<j} exp(-r_ij / tau),
+ * evaluated for the FP32 projection P (n x k, need not be orthonormal, r is
+ * then ||P^T s||).  The scalar L is written to loss[0] (device FP32).  The
+ * handle keeps what the backward needs (Y and L), so sap_softmin_bwd must
+ * follow its sap_softmin_fwd with the same P and tau.  tau > 0. */
+sap_status sap_softmin_fwd(sap_handle h, const float *P, double tau,
+                           float *loss);
+
+/* Gradient: dP = grad_loss[0] * dL/dP = g * sum w_ij s_ij (P^T s_ij)^T / r_ij,
+ * w_ij = exp(-(r_ij - L)/tau).  dP is n x k FP32 (overwritten).  Pairs with
+ * r_ij = 0 contribute nothing. */
+sap_status sap_softmin_bwd(sap_handle h, const float *P, double tau,
+                           const float *grad_loss, float *dP);
+
+/* Free everything the handle owns.  NULL is accepted. */
+sap_status sap_destroy(sap_handle h);
+
+/* Last error message of the handle, or of the calling thread if h is NULL
+ * (errors from sap_init).  Never NULL; valid until the next call on h. */
+const char *sap_last_error(sap_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAP_H */

@@ -60,6 +60,7 @@ def _load():
         lib.oracle_pair_r.argtypes = [p, i64, i32, p, i32, i64, i64,
                                       C.POINTER(d), C.POINTER(d)]
         lib.oracle_all_r.argtypes = [p, i64, i32, p, i32, d, p, p]
+        lib.oracle_pairs_r.argtypes = [p, i64, i32, p, i32, p, i64, p]
         lib.oracle_step.argtypes = [p, i32, i32, p, d, i32, p, C.POINTER(i32)]
         lib.oracle_orth_error.argtypes = [p, i32, i32]
         lib.oracle_orth_error.restype = d
@@ -129,6 +130,17 @@ def pair_r(X, P, i: int, j: int) -> tuple[float, float]:
                                int(i), int(j), C.byref(r), C.byref(d))
     _check(st, "pair_r")
     return r.value, d.value
+
+
+def pairs_r(X, P, ij) -> np.ndarray:
+    """r of each pair in ij (count x 2 integer array)."""
+    X, P = _X(X), _P(P)
+    ij = np.ascontiguousarray(ij, dtype=np.int64).reshape(-1, 2)
+    r = np.empty(ij.shape[0])
+    st = _load().oracle_pairs_r(_ptr(X), X.shape[0], X.shape[1], _ptr(P), P.shape[1],
+                                _ptr(ij), ij.shape[0], _ptr(r))
+    _check(st, "pairs_r")
+    return r
 
 
 def all_r(X, P, min_len: float = 0.0) -> tuple[np.ndarray, np.ndarray]:

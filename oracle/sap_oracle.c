@@ -226,6 +226,38 @@ int oracle_pair_r(const double *X, int64_t N, int32_t n, const double *P,
     return ORACLE_OK;
 }
 
+/* r of a list of pairs ij[2e], ij[2e+1] (NaN for a duplicate). */
+int oracle_pairs_r(const double *X, int64_t N, int32_t n, const double *P,
+                   int32_t k, const int64_t *ij, int64_t count, double *r_out) {
+    if (!X || !P || !ij || !r_out || count < 0) return ORACLE_EARG;
+    for (int64_t e = 0; e < count; ++e) {
+        int64_t i = ij[2 * e], j = ij[2 * e + 1];
+        if (i < 0 || j < 0 || i >= N || j >= N || i == j) return ORACLE_EARG;
+    }
+    int fail = 0;
+#pragma omp parallel
+    {
+        double *s = (double *)malloc(sizeof(double) * (size_t)n);
+        double *c = (double *)malloc(sizeof(double) * (size_t)k);
+        const int ok = s && c;
+        if (!ok) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(static)
+        for (int64_t e = 0; e < count; ++e) {
+            if (!ok) continue;
+            int64_t i = ij[2 * e], j = ij[2 * e + 1];
+            int64_t a = i < j ? i : j, b = i < j ? j : i;
+            double d = unit_secant(X, n, a, b, s);
+            r_out[e] = d > 0.0 ? project_norm(P, n, k, s, c) : NAN;
+        }
+        free(s);
+        free(c);
+    }
+    return fail ? ORACLE_ENOMEM : ORACLE_OK;
+}
+
 /* Every pair's r (NaN for a dropped pair) and d, in pair-index order. */
 int oracle_all_r(const double *X, int64_t N, int32_t n, const double *P,
                  int32_t k, double min_len, double *r_out, double *d_out) {

@@ -1,0 +1,597 @@
+// Host runtime of the SAP library: argument validation, buffer ownership,
+// launch sequencing and the extern "C" entry points declared in sap.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "sap_common.h"
+
+// The kernels are compiled into this translation unit (one code object).
+#include "sap_init.hip"
+#include "sap_iter.hip"
+
+using namespace sap;
+
+// ---------------------------------------------------------------- context
+
+struct sap_ctx {
+    sap_config cfg{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool poisoned = false;
+    std::string err;
+
+    const void *X = nullptr;
+    int64_t ldx = 0, N = 0, p = 0;
+    int n = 0, k = 0, kp = 0;
+
+    // fused
+    int64_t nb = 0, Npad = 0, ntiles = 0, nclose = 0;
+    int2 *d_tiles = nullptr;
+    float4 *d_invd2 = nullptr;
+    float *d_Y = nullptr;
+    int2 *d_close = nullptr;
+
+    // plain
+    void *d_S = nullptr;
+    int64_t pcols = 0, nchunks = 0;
+    void *d_Pr = nullptr;
+
+    // common
+    double *d_P64t = nullptr;
+    double *d_mu = nullptr;
+    uint32_t *d_tmin = nullptr;
+    DevState *d_st = nullptr;
+    Partial *d_part = nullptr;
+    DevResult *d_res = nullptr;
+    int pass_grid = 0, rescore_grid = 0;
+    size_t tail_lds = 0;
+
+    double radius = 0, close_d = 0, e_abs = 0, e_rel = 0;
+    int64_t kept = 0, dropped = 0;
+    int64_t dev_bytes = 0;
+    std::vector<void *> allocs;
+};
+
+static thread_local std::string g_tls_err;
+
+static sap_status fail(sap_ctx *h, sap_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) {
+        h->err = buf;
+        if (st == SAP_ERR_DEVICE) h->poisoned = true;
+    }
+    g_tls_err = buf;
+    return st;
+}
+
+#define SAP_HIP(h, expr)                                                                  \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            if (e_ == hipErrorOutOfMemory)                                                \
+                return fail(h, SAP_ERR_OUT_OF_MEMORY, "%s: %s", #expr, hipGetErrorString(e_)); \
+            return fail(h, SAP_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));     \
+        }                                                                                 \
+    } while (0)
+
+#define SAP_LAUNCHED(h, what)                                                             \
+    do {                                                                                  \
+        hipError_t e_ = hipGetLastError();                                                \
+        if (e_ != hipSuccess)                                                             \
+            return fail(h, SAP_ERR_DEVICE, "launch of %s: %s", what, hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+static sap_status dalloc(sap_ctx *h, T **ptr, size_t bytes) {
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, e == hipErrorOutOfMemory ? SAP_ERR_OUT_OF_MEMORY : SAP_ERR_DEVICE,
+                    "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+    }
+    h->allocs.push_back(p);
+    h->dev_bytes += (int64_t)bytes;
+    *ptr = static_cast<T *>(p);
+    return SAP_OK;
+}
+
+#define SAP_TRY(expr)                        \
+    do {                                     \
+        sap_status s_ = (expr);              \
+        if (s_ != SAP_OK) return s_;         \
+    } while (0)
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+static constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
+static constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53
+
+// Validation of a configuration; no HIP call.  Shared with sap_init.
+static sap_status validate(const sap_config *c, int64_t ldx, const void *X, const void *P0,
+                           const void *out) {
+    if (!c || !X || !P0 || !out) return fail(nullptr, SAP_ERR_INVALID_ARG, "null pointer argument");
+    if (c->N < 2) return fail(nullptr, SAP_ERR_INVALID_ARG, "N must be >= 2 (got %lld)", (long long)c->N);
+    if (c->N >= (1ll << 31) - 64)
+        return fail(nullptr, SAP_ERR_UNSUPPORTED, "N must be < 2^31 - 64");
+    if (c->n < 1) return fail(nullptr, SAP_ERR_INVALID_ARG, "n must be >= 1");
+    if (c->k < 1 || c->k > c->n)
+        return fail(nullptr, SAP_ERR_INVALID_ARG, "k must satisfy 1 <= k <= n (k=%d, n=%d)", c->k, c->n);
+    if (c->k > kMaxK) return fail(nullptr, SAP_ERR_UNSUPPORTED, "k > %d is not supported", kMaxK);
+    if ((int64_t)c->n * (c->k + 3) > 19200)
+        return fail(nullptr, SAP_ERR_UNSUPPORTED, "n*(k+3) must be <= 19200 (the update runs in LDS)");
+    if (c->dtype != SAP_F64 && c->dtype != SAP_F32)
+        return fail(nullptr, SAP_ERR_INVALID_ARG, "dtype must be SAP_F64 or SAP_F32");
+    if (c->form != SAP_PLAIN && c->form != SAP_FUSED)
+        return fail(nullptr, SAP_ERR_INVALID_ARG, "form must be SAP_PLAIN or SAP_FUSED");
+    if (c->rule != SAP_STEP_LITERAL && c->rule != SAP_STEP_NORMALIZED)
+        return fail(nullptr, SAP_ERR_INVALID_ARG, "rule must be SAP_STEP_LITERAL or SAP_STEP_NORMALIZED");
+    if (!(c->alpha >= 0.0 && c->alpha <= 1.0))
+        return fail(nullptr, SAP_ERR_INVALID_ARG, "alpha must lie in [0, 1]");
+    if (!(c->min_len >= 0.0) || !std::isfinite(c->min_len))
+        return fail(nullptr, SAP_ERR_INVALID_ARG, "min_len must be finite and >= 0");
+    if (std::isnan(c->close_d) || std::isinf(c->close_d))
+        return fail(nullptr, SAP_ERR_INVALID_ARG, "close_d must be finite (< 0 = automatic)");
+    if (c->close_cap < 0) return fail(nullptr, SAP_ERR_INVALID_ARG, "close_cap must be >= 0");
+    if (ldx < c->n) return fail(nullptr, SAP_ERR_INVALID_ARG, "ldx must be >= n");
+    return SAP_OK;
+}
+
+static sap_status check_P_host(sap_ctx *h, const std::vector<double> &P, int n, int k) {
+    for (double v : P)
+        if (!std::isfinite(v)) return fail(h, SAP_ERR_NONFINITE, "P holds NaN or Inf");
+    double e = 0.0;
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) {
+            double acc = 0.0;
+            for (int l = 0; l < n; ++l) acc += P[(size_t)l * k + a] * P[(size_t)l * k + b];
+            e = std::max(e, std::fabs(acc - (a == b ? 1.0 : 0.0)));
+        }
+    if (e > 1e-6) return fail(h, SAP_ERR_NOT_ORTHONORMAL, "max |P^T P - I| = %.3g > 1e-6", e);
+    return SAP_OK;
+}
+
+// Load a device P (n x k row-major) into the FP64 master (k x n) after checks.
+static sap_status load_P(sap_ctx *h, const double *P_dev) {
+    const int n = h->n, k = h->k;
+    std::vector<double> P((size_t)n * k), Pt((size_t)n * k);
+    SAP_HIP(h, hipMemcpyAsync(P.data(), P_dev, sizeof(double) * n * k, hipMemcpyDeviceToHost, h->stream));
+    SAP_HIP(h, hipStreamSynchronize(h->stream));
+    SAP_TRY(check_P_host(h, P, n, k));
+    for (int l = 0; l < n; ++l)
+        for (int q = 0; q < k; ++q) Pt[(size_t)q * n + l] = P[(size_t)l * k + q];
+    SAP_HIP(h, hipMemcpyAsync(h->d_P64t, Pt.data(), sizeof(double) * n * k, hipMemcpyHostToDevice,
+                              h->stream));
+    if (h->cfg.form == SAP_PLAIN) {
+        const int blocks = (int)ceil_div((int64_t)n * k, 256);
+        if (h->cfg.dtype == SAP_F32)
+            hipLaunchKernelGGL(k_write_pass_P<float>, dim3(blocks), dim3(256), 0, h->stream,
+                               h->d_P64t, n, k, static_cast<float *>(h->d_Pr));
+        else
+            hipLaunchKernelGGL(k_write_pass_P<double>, dim3(blocks), dim3(256), 0, h->stream,
+                               h->d_P64t, n, k, static_cast<double *>(h->d_Pr));
+        SAP_LAUNCHED(h, "k_write_pass_P");
+    }
+    SAP_HIP(h, hipStreamSynchronize(h->stream));
+    return SAP_OK;
+}
+
+// ---------------------------------------------------------------- init pieces
+
+static sap_status init_moments(sap_ctx *h) {
+    const int64_t rows = 256;
+    const int64_t nblk = ceil_div(h->N, rows);
+    double *part = nullptr;
+    SAP_TRY(dalloc(h, &part, sizeof(double) * nblk * h->n));
+    SAP_HIP(h, hipMemsetAsync(h->d_st, 0, sizeof(DevState), h->stream));
+    hipLaunchKernelGGL(k_col_partial, dim3((unsigned)nblk), dim3(256), 0, h->stream, h->X,
+                       h->cfg.dtype, h->ldx, h->N, h->n, rows, part, &h->d_st->nonfinite);
+    SAP_LAUNCHED(h, "k_col_partial");
+    hipLaunchKernelGGL(k_col_mean, dim3((unsigned)ceil_div(h->n, 256)), dim3(256), 0, h->stream,
+                       part, nblk, h->n, h->N, h->d_mu);
+    SAP_LAUNCHED(h, "k_col_mean");
+    hipLaunchKernelGGL(k_radius, dim3((unsigned)ceil_div(h->N, 4)), dim3(256), 0, h->stream, h->X,
+                       h->cfg.dtype, h->ldx, h->N, h->n, h->d_mu,
+                       reinterpret_cast<unsigned long long *>(&h->d_st->radius_bits));
+    SAP_LAUNCHED(h, "k_radius");
+    DevState st;
+    SAP_HIP(h, hipMemcpyAsync(&st, h->d_st, sizeof st, hipMemcpyDeviceToHost, h->stream));
+    SAP_HIP(h, hipStreamSynchronize(h->stream));
+    if (st.nonfinite) return fail(h, SAP_ERR_NONFINITE, "X holds NaN or Inf");
+    double r;
+    std::memcpy(&r, &st.radius_bits, sizeof r);
+    h->radius = r;
+    return SAP_OK;
+}
+
+static sap_status init_plain(sap_ctx *h) {
+    const bool f64 = h->cfg.dtype == SAP_F64;
+    const size_t es = f64 ? 8 : 4;
+    h->pcols = ceil_div(h->p, kChunk) * kChunk;
+    h->nchunks = h->pcols / kChunk;
+    SAP_TRY(dalloc(h, &h->d_S, es * (size_t)h->n * (size_t)h->pcols));
+    SAP_TRY(dalloc(h, &h->d_Pr, es * (size_t)h->n * h->k));
+    SAP_TRY(dalloc(h, &h->d_tmin, sizeof(uint32_t) * h->nchunks));
+    const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(h->pcols, 256), 65536);
+    auto *kept = reinterpret_cast<unsigned long long *>(&h->d_st->kept);
+    auto *drop = reinterpret_cast<unsigned long long *>(&h->d_st->dropped);
+    if (f64)
+        hipLaunchKernelGGL(k_build_secants<double>, dim3(grid), dim3(256), 0, h->stream, h->X,
+                           h->cfg.dtype, h->ldx, h->N, h->n, h->cfg.min_len,
+                           static_cast<double *>(h->d_S), h->pcols, h->p, kept, drop);
+    else
+        hipLaunchKernelGGL(k_build_secants<float>, dim3(grid), dim3(256), 0, h->stream, h->X,
+                           h->cfg.dtype, h->ldx, h->N, h->n, h->cfg.min_len,
+                           static_cast<float *>(h->d_S), h->pcols, h->p, kept, drop);
+    SAP_LAUNCHED(h, "k_build_secants");
+    DevState st;
+    SAP_HIP(h, hipMemcpyAsync(&st, h->d_st, sizeof st, hipMemcpyDeviceToHost, h->stream));
+    SAP_HIP(h, hipStreamSynchronize(h->stream));
+    h->kept = st.kept;
+    h->dropped = st.dropped;
+    // |c~ - c| <= (n+3) u sqrt(k) (rounded secants and P, FMA accumulation),
+    // and the final sum of squares adds (k+2) u relative.
+    const double u = f64 ? kU64 : kU32;
+    h->e_abs = (h->n + 3) * u * std::sqrt((double)h->k) * 1.01;
+    h->e_rel = (h->k + 4) * u + (f64 ? 2.0 * kU32 : 0.0);
+    h->pass_grid = (int)std::min<int64_t>(ceil_div(h->nchunks, 4), 2048);
+    return SAP_OK;
+}
+
+static sap_status init_fused(sap_ctx *h) {
+    h->nb = ceil_div(h->N, kTile);
+    h->Npad = h->nb * kTile;
+    h->ntiles = h->nb * (h->nb + 1) / 2;
+    h->kp = h->k <= 4 ? 4 : (h->k <= 8 ? 8 : (h->k <= 12 ? 12 : 16));
+    std::vector<int2> tiles((size_t)h->ntiles);
+    for (int64_t bi = 0, t = 0; bi < h->nb; ++bi)
+        for (int64_t bj = bi; bj < h->nb; ++bj, ++t) tiles[(size_t)t] = make_int2((int)bi, (int)bj);
+    SAP_TRY(dalloc(h, &h->d_tiles, sizeof(int2) * h->ntiles));
+    SAP_TRY(dalloc(h, &h->d_invd2, sizeof(float) * (size_t)h->ntiles * kTileElems));
+    SAP_TRY(dalloc(h, &h->d_Y, sizeof(float) * (size_t)h->Npad * h->kp));
+    SAP_TRY(dalloc(h, &h->d_tmin, sizeof(uint32_t) * h->ntiles));
+    SAP_HIP(h, hipMemcpyAsync(h->d_tiles, tiles.data(), sizeof(int2) * h->ntiles,
+                              hipMemcpyHostToDevice, h->stream));
+
+    // Coarse error: ||y~_i - y_i|| <= u32 ||y_i|| + FP64 terms <= R (u32 + ...),
+    // so |r~ - r| <= 2 R (u32 + ...) / d.  The automatic cutoff aims at an
+    // absolute error of 1e-6 for every pair left to the coarse pass.
+    const double delta = h->radius * (kU32 * 1.001 + (h->n + 2) * std::sqrt((double)h->k) * kU64 * 4.0);
+    const bool automatic = h->cfg.close_d < 0.0;
+    double dtarget = automatic ? 2.0 * delta / 1e-6 : h->cfg.close_d;
+    std::vector<float> ladder(64);
+    for (int m = 0; m < 64; ++m) {
+        const double D = dtarget * std::pow(2.0, -m / 4.0);
+        ladder[m] = D > 0.0 ? (float)(1.0 / (D * D)) : std::numeric_limits<float>::infinity();
+    }
+    float *d_ladder = nullptr;
+    SAP_TRY(dalloc(h, &d_ladder, sizeof(float) * 64));
+    SAP_HIP(h, hipMemcpyAsync(d_ladder, ladder.data(), sizeof(float) * 64, hipMemcpyHostToDevice, h->stream));
+    const unsigned grid = (unsigned)std::min<int64_t>(h->ntiles, 8192);
+    hipLaunchKernelGGL(k_build_invd2, dim3(grid), dim3(256), 0, h->stream, h->X, h->cfg.dtype,
+                       h->ldx, h->N, h->n, h->d_tiles, h->ntiles, h->cfg.min_len, h->d_invd2,
+                       d_ladder, reinterpret_cast<unsigned long long *>(h->d_st->hist),
+                       reinterpret_cast<unsigned long long *>(&h->d_st->kept),
+                       reinterpret_cast<unsigned long long *>(&h->d_st->dropped));
+    SAP_LAUNCHED(h, "k_build_invd2");
+    DevState st;
+    SAP_HIP(h, hipMemcpyAsync(&st, h->d_st, sizeof st, hipMemcpyDeviceToHost, h->stream));
+    SAP_HIP(h, hipStreamSynchronize(h->stream));
+    h->kept = st.kept;
+    h->dropped = st.dropped;
+    if (h->kept == 0) return SAP_OK;  // caller reports SAP_ERR_NO_PAIRS
+
+    const int64_t cap = h->cfg.close_cap > 0
+                            ? h->cfg.close_cap
+                            : std::min<int64_t>(1 << 20, std::max<int64_t>(1024, h->p / (4 * h->n)));
+    // count(1/d^2 > ladder[m]) = sum of bins m..63
+    int msel = -1;
+    uint64_t tail = 0;
+    std::vector<uint64_t> above(64);
+    for (int m = 63; m >= 0; --m) { tail += st.hist[m]; above[m] = tail; }
+    if (automatic) {
+        for (int m = 0; m < 64; ++m)
+            if ((int64_t)above[m] <= cap) { msel = m; break; }
+        if (msel < 0)
+            return fail(h, SAP_ERR_CAPACITY,
+                        "%llu pairs are closer than %.3g: above the short-pair cap %lld",
+                        (unsigned long long)above[63], dtarget * std::pow(2.0, -63 / 4.0), (long long)cap);
+    } else {
+        if ((int64_t)above[0] > cap)
+            return fail(h, SAP_ERR_CAPACITY, "%llu pairs are closer than close_d=%.3g: above close_cap %lld",
+                        (unsigned long long)above[0], dtarget, (long long)cap);
+        msel = 0;
+    }
+    const float thr = ladder[msel];
+    const int64_t want = (int64_t)above[msel];
+    if (want > 0) {
+        SAP_TRY(dalloc(h, &h->d_close, sizeof(int2) * want));
+        unsigned long long *d_count = reinterpret_cast<unsigned long long *>(&h->d_st->n_close);
+        hipLaunchKernelGGL(k_mark_close, dim3(grid), dim3(256), 0, h->stream, h->d_invd2, h->d_tiles,
+                           h->ntiles, thr, h->d_close, want, d_count);
+        SAP_LAUNCHED(h, "k_mark_close");
+        SAP_HIP(h, hipMemcpyAsync(&st, h->d_st, sizeof st, hipMemcpyDeviceToHost, h->stream));
+        SAP_HIP(h, hipStreamSynchronize(h->stream));
+        if (st.n_close != want)
+            return fail(h, SAP_ERR_DEVICE, "short-pair count mismatch (%lld vs %lld)",
+                        (long long)st.n_close, (long long)want);
+        // deterministic order: sort by (i, j)
+        std::vector<int2> lst((size_t)want);
+        SAP_HIP(h, hipMemcpyAsync(lst.data(), h->d_close, sizeof(int2) * want, hipMemcpyDeviceToHost, h->stream));
+        SAP_HIP(h, hipStreamSynchronize(h->stream));
+        std::sort(lst.begin(), lst.end(), [](const int2 &a, const int2 &b) {
+            return a.x != b.x ? a.x < b.x : a.y < b.y;
+        });
+        SAP_HIP(h, hipMemcpyAsync(h->d_close, lst.data(), sizeof(int2) * want, hipMemcpyHostToDevice, h->stream));
+    }
+    h->nclose = want;
+    // non-close pairs satisfy fl32(1/d^2) <= thr, hence d >= 1/sqrt(thr (1 + 2^-22))
+    const double Deff = 1.0 / std::sqrt((double)thr * (1.0 + std::ldexp(1.0, -22)));
+    h->close_d = dtarget * std::pow(2.0, -msel / 4.0);
+    h->e_abs = 2.0 * delta / Deff;
+    h->e_rel = (h->k + 4) * kU32;
+    h->pass_grid = (int)std::min<int64_t>(ceil_div(h->ntiles, 4), 2048);
+    return SAP_OK;
+}
+
+// ---------------------------------------------------------------- iteration
+
+// Enqueue one evaluation (+ update when do_step).
+static sap_status enqueue_eval(sap_ctx *h, int do_step, double *tr_min, int64_t *tr_ij,
+                               int32_t *tr_cert, int it) {
+    const int K = h->k;
+    const bool f64 = h->cfg.dtype == SAP_F64;
+    uint32_t *gmin = &h->d_st->gmin;
+    if (h->cfg.form == SAP_FUSED) {
+        hipLaunchKernelGGL(k_gemm_y, dim3((unsigned)(h->Npad / 64)), dim3(256), 0, h->stream, h->X,
+                           h->cfg.dtype, h->ldx, h->N, h->n, h->k, h->d_mu, h->d_P64t, h->d_Y,
+                           h->kp, h->Npad);
+        SAP_LAUNCHED(h, "k_gemm_y");
+        SAP_DISPATCH_K(K, hipLaunchKernelGGL(k_pair_fused<K>, dim3(h->pass_grid), dim3(kPairBlock),
+                                             0, h->stream, h->d_Y, h->kp, h->d_invd2, h->d_tiles,
+                                             h->ntiles, h->d_tmin, gmin));
+        SAP_LAUNCHED(h, "k_pair_fused");
+        if (f64) {
+            SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_rescore_fused<K, double>), dim3(h->rescore_grid),
+                                                 dim3(kPairBlock), 0, h->stream, h->d_Y, h->kp,
+                                                 h->d_invd2, h->d_tiles, h->ntiles, h->d_tmin, gmin,
+                                                 h->e_abs, h->e_rel, static_cast<const double *>(h->X),
+                                                 h->ldx, h->n, h->d_P64t, h->d_close, h->nclose,
+                                                 h->d_part));
+        } else {
+            SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_rescore_fused<K, float>), dim3(h->rescore_grid),
+                                                 dim3(kPairBlock), 0, h->stream, h->d_Y, h->kp,
+                                                 h->d_invd2, h->d_tiles, h->ntiles, h->d_tmin, gmin,
+                                                 h->e_abs, h->e_rel, static_cast<const float *>(h->X),
+                                                 h->ldx, h->n, h->d_P64t, h->d_close, h->nclose,
+                                                 h->d_part));
+        }
+        SAP_LAUNCHED(h, "k_rescore_fused");
+    } else {
+        if (f64) {
+            const double *S = static_cast<const double *>(h->d_S);
+            const double *Pr = static_cast<const double *>(h->d_Pr);
+            SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_pair_plain<K, double>), dim3(h->pass_grid),
+                                                 dim3(kPairBlock), 0, h->stream, S, h->pcols, h->n,
+                                                 Pr, h->nchunks, h->d_tmin, gmin));
+            SAP_LAUNCHED(h, "k_pair_plain");
+            SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_rescore_plain<K, double>), dim3(h->rescore_grid),
+                                                 dim3(kPairBlock), 0, h->stream, S, h->pcols, h->n,
+                                                 Pr, h->nchunks, h->d_tmin, gmin, h->e_abs, h->e_rel,
+                                                 static_cast<const double *>(h->X), h->ldx, h->N,
+                                                 h->d_P64t, h->d_part));
+        } else {
+            const float *S = static_cast<const float *>(h->d_S);
+            const float *Pr = static_cast<const float *>(h->d_Pr);
+            SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_pair_plain<K, float>), dim3(h->pass_grid),
+                                                 dim3(kPairBlock), 0, h->stream, S, h->pcols, h->n,
+                                                 Pr, h->nchunks, h->d_tmin, gmin));
+            SAP_LAUNCHED(h, "k_pair_plain");
+            SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_rescore_plain<K, float>), dim3(h->rescore_grid),
+                                                 dim3(kPairBlock), 0, h->stream, S, h->pcols, h->n,
+                                                 Pr, h->nchunks, h->d_tmin, gmin, h->e_abs, h->e_rel,
+                                                 static_cast<const float *>(h->X), h->ldx, h->N,
+                                                 h->d_P64t, h->d_part));
+        }
+        SAP_LAUNCHED(h, "k_rescore_plain");
+    }
+    const int pr_kind = h->cfg.form == SAP_PLAIN ? (f64 ? 2 : 1) : 0;
+    if (f64)
+        hipLaunchKernelGGL(k_tail<double>, dim3(1), dim3(64), h->tail_lds, h->stream, h->d_part,
+                           h->rescore_grid, gmin, h->e_abs, h->e_rel,
+                           static_cast<const double *>(h->X), h->ldx, h->N, h->n, h->k, h->d_P64t,
+                           h->d_Pr, pr_kind, h->cfg.alpha, h->cfg.rule, do_step, h->d_res, tr_min,
+                           tr_ij, tr_cert, it);
+    else
+        hipLaunchKernelGGL(k_tail<float>, dim3(1), dim3(64), h->tail_lds, h->stream, h->d_part,
+                           h->rescore_grid, gmin, h->e_abs, h->e_rel,
+                           static_cast<const float *>(h->X), h->ldx, h->N, h->n, h->k, h->d_P64t,
+                           h->d_Pr, pr_kind, h->cfg.alpha, h->cfg.rule, do_step, h->d_res, tr_min,
+                           tr_ij, tr_cert, it);
+    SAP_LAUNCHED(h, "k_tail");
+    return SAP_OK;
+}
+
+static sap_status read_result(sap_ctx *h, sap_min_result *out) {
+    DevResult r;
+    SAP_HIP(h, hipMemcpyAsync(&r, h->d_res, sizeof r, hipMemcpyDeviceToHost, h->stream));
+    SAP_HIP(h, hipStreamSynchronize(h->stream));
+    out->min_norm = r.min_norm;
+    out->i = r.i;
+    out->j = r.j;
+    out->pair_index = r.q;
+    out->coarse_min = r.coarse_min;
+    out->window = r.window;
+    out->certified = r.certified;
+    out->n_rescored = r.n_rescored;
+    out->t = r.t;
+    out->reserved = r.n_tiles;
+    return SAP_OK;
+}
+
+static sap_status usable(sap_ctx *h) {
+    if (!h) return fail(nullptr, SAP_ERR_INVALID_ARG, "null handle");
+    if (h->poisoned) return fail(h, SAP_ERR_POISONED, "handle poisoned by an earlier device error: %s", h->err.c_str());
+    SAP_HIP(h, hipSetDevice(h->device));
+    return SAP_OK;
+}
+
+static void destroy_ctx(sap_ctx *h) {
+    if (!h) return;
+    for (void *p : h->allocs) (void)hipFree(p);
+    delete h;
+}
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+sap_status sap_init(const sap_config *cfg, const void *X, int64_t ldx, const double *P0,
+                    void *stream, sap_handle *out) {
+    if (out) *out = nullptr;
+    SAP_TRY(validate(cfg, ldx, X, P0, out));
+    sap_ctx *h = new sap_ctx();
+    h->cfg = *cfg;
+    h->X = X;
+    h->ldx = ldx;
+    h->N = cfg->N;
+    h->n = cfg->n;
+    h->k = cfg->k;
+    h->kp = cfg->k;
+    h->p = cfg->N * (cfg->N - 1) / 2;
+    h->stream = static_cast<hipStream_t>(stream);
+    auto bail = [&](sap_status s) {
+        g_tls_err = h->err.empty() ? g_tls_err : h->err;
+        destroy_ctx(h);
+        return s;
+    };
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) return bail(fail(h, SAP_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
+    sap_status s;
+    if ((s = dalloc(h, &h->d_P64t, sizeof(double) * h->n * h->k)) != SAP_OK) return bail(s);
+    if ((s = dalloc(h, &h->d_mu, sizeof(double) * h->n)) != SAP_OK) return bail(s);
+    if ((s = dalloc(h, &h->d_st, sizeof(DevState))) != SAP_OK) return bail(s);
+    if ((s = dalloc(h, &h->d_res, sizeof(DevResult))) != SAP_OK) return bail(s);
+    h->rescore_grid = 256;
+    if ((s = dalloc(h, &h->d_part, sizeof(Partial) * h->rescore_grid)) != SAP_OK) return bail(s);
+    if ((s = init_moments(h)) != SAP_OK) return bail(s);
+    if ((s = (cfg->form == SAP_PLAIN ? init_plain(h) : init_fused(h))) != SAP_OK) return bail(s);
+    if (h->kept == 0) return bail(fail(h, SAP_ERR_NO_PAIRS, "every pair is a duplicate or shorter than min_len"));
+    if ((s = load_P(h, P0)) != SAP_OK) return bail(s);
+    h->tail_lds = sizeof(double) * ((size_t)h->k * h->n + 2 * (size_t)h->n + 16);
+    const void *tails[2] = {reinterpret_cast<const void *>(&k_tail<float>),
+                            reinterpret_cast<const void *>(&k_tail<double>)};
+    for (const void *f : tails) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->tail_lds);
+        if (e != hipSuccess) return bail(fail(h, SAP_ERR_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(e)));
+    }
+    hipLaunchKernelGGL(k_arm_gmin, dim3(1), dim3(1), 0, h->stream, &h->d_st->gmin);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return bail(fail(h, SAP_ERR_DEVICE, "init: %s", hipGetErrorString(e)));
+    *out = h;
+    return SAP_OK;
+}
+
+sap_status sap_min_secant(sap_handle h, sap_min_result *out) {
+    SAP_TRY(usable(h));
+    if (!out) return fail(h, SAP_ERR_INVALID_ARG, "null result pointer");
+    SAP_TRY(enqueue_eval(h, 0, nullptr, nullptr, nullptr, 0));
+    return read_result(h, out);
+}
+
+sap_status sap_step(sap_handle h, sap_min_result *out) {
+    SAP_TRY(usable(h));
+    SAP_TRY(enqueue_eval(h, 1, nullptr, nullptr, nullptr, 0));
+    if (out) return read_result(h, out);
+    return SAP_OK;
+}
+
+sap_status sap_run(sap_handle h, int32_t iters, double *min_trace, int64_t *ij_trace,
+                   int32_t *cert_trace) {
+    SAP_TRY(usable(h));
+    if (iters < 0) return fail(h, SAP_ERR_INVALID_ARG, "iters must be >= 0");
+    if (!min_trace) return fail(h, SAP_ERR_INVALID_ARG, "min_trace must not be NULL");
+    for (int32_t it = 0; it <= iters; ++it)
+        SAP_TRY(enqueue_eval(h, it < iters ? 1 : 0, min_trace, ij_trace, cert_trace, it));
+    return SAP_OK;
+}
+
+sap_status sap_get_P(sap_handle h, double *P_out) {
+    SAP_TRY(usable(h));
+    if (!P_out) return fail(h, SAP_ERR_INVALID_ARG, "null P_out");
+    hipLaunchKernelGGL(k_P_out, dim3((unsigned)ceil_div((int64_t)h->n * h->k, 256)), dim3(256), 0,
+                       h->stream, h->d_P64t, h->n, h->k, P_out);
+    SAP_LAUNCHED(h, "k_P_out");
+    return SAP_OK;
+}
+
+sap_status sap_set_P(sap_handle h, const double *P) {
+    SAP_TRY(usable(h));
+    if (!P) return fail(h, SAP_ERR_INVALID_ARG, "null P");
+    return load_P(h, P);
+}
+
+sap_status sap_set_stream(sap_handle h, void *stream) {
+    SAP_TRY(usable(h));
+    h->stream = static_cast<hipStream_t>(stream);
+    return SAP_OK;
+}
+
+sap_status sap_info(sap_handle h, sap_info_t *out) {
+    SAP_TRY(usable(h));
+    if (!out) return fail(h, SAP_ERR_INVALID_ARG, "null info pointer");
+    SAP_HIP(h, hipStreamSynchronize(h->stream));
+    out->n_pairs = h->kept;
+    out->n_dropped = h->dropped;
+    out->n_close = h->nclose;
+    out->close_d = h->cfg.form == SAP_FUSED ? h->close_d : 0.0;
+    out->e_abs = h->e_abs;
+    out->e_rel = h->e_rel;
+    out->radius = h->radius;
+    if (h->cfg.form == SAP_FUSED)
+        out->bytes_per_iter = (int64_t)h->ntiles * kTileElems * 4;
+    else
+        out->bytes_per_iter = (int64_t)h->n * h->pcols * (h->cfg.dtype == SAP_F64 ? 8 : 4);
+    out->device_bytes = h->dev_bytes;
+    out->n_tiles = h->cfg.form == SAP_FUSED ? h->ntiles : h->nchunks;
+    return SAP_OK;
+}
+
+sap_status sap_softmin_fwd(sap_handle h, const float *P, double tau, float *loss) {
+    SAP_TRY(usable(h));
+    (void)P; (void)tau; (void)loss;
+    return fail(h, SAP_ERR_UNSUPPORTED, "soft-min is not available in this build");
+}
+
+sap_status sap_softmin_bwd(sap_handle h, const float *P, double tau, const float *grad_loss,
+                           float *dP) {
+    SAP_TRY(usable(h));
+    (void)P; (void)tau; (void)grad_loss; (void)dP;
+    return fail(h, SAP_ERR_UNSUPPORTED, "soft-min is not available in this build");
+}
+
+sap_status sap_destroy(sap_handle h) {
+    if (!h) return SAP_OK;
+    (void)hipSetDevice(h->device);
+    if (!h->poisoned) (void)hipStreamSynchronize(h->stream);
+    destroy_ctx(h);
+    return SAP_OK;
+}
+
+const char *sap_last_error(sap_handle h) {
+    if (h) return h->err.c_str();
+    return g_tls_err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// the SAP library.  Not part of the public ABI (that is include/sap.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sap.h"
+
+namespace sap {
+
+constexpr int kWave = 64;           // CDNA wavefront width
+constexpr int kTile = 64;           // fused pass: 64 x 64 point-pair tiles
+constexpr int kTileElems = kTile * kTile;
+constexpr int kChunk = 256;         // plain pass: 256 consecutive pairs per chunk
+constexpr int kMaxK = 16;           // widest projection handled (one MFMA N-tile)
+constexpr int kPairBlock = 256;     // threads per block of the pair passes
+constexpr uint32_t kKeyNone = 0xFFFFFFFFu;  // "no pair": loses every unsigned min
+
+// Sentinels stored in the fused 1/d^2 array.  Both are negative, so the
+// product with a sum of squares is <= -0.0, whose bit pattern as an
+// unsigned integer exceeds that of every non-negative float: masked pairs
+// lose the unsigned minimum without a branch.
+constexpr float kMaskDropped = -1.0f;  // padding, i >= j, duplicate, d < l
+constexpr float kMaskClose = -2.0f;    // evaluated in FP64 from the close list
+
+// Per-block result of the FP64 rescoring kernel.
+struct Partial {
+    double r;       // best FP64 r in the block (+inf if none)
+    int32_t i, j;   // its pair
+    int32_t n_rescored;
+    int32_t n_tiles;  // window tiles revisited by the block
+    int32_t n_viol;   // rescored pairs whose coarse value broke the error bound
+    int32_t pad;
+};
+
+// Device-resident record of the last evaluation (read back by the host).
+struct DevResult {
+    double min_norm;
+    int64_t i, j, q;
+    double coarse_min;
+    double window;
+    int32_t certified;
+    int32_t n_rescored;
+    int32_t t;
+    int32_t n_tiles;
+};
+
+// Mutable device-side scalars of a handle.
+struct DevState {
+    uint32_t gmin;       // min coarse key (bits of r~^2) over non-close pairs
+    uint32_t pad;
+    double radius;       // max_i ||x_i - mu|| (init)
+    uint64_t radius_bits;
+    int32_t nonfinite;   // init: X held NaN/Inf
+    int32_t pad2;
+    int64_t kept, dropped;  // init pair counts
+    uint64_t hist[64];   // init: close-pair ladder counts
+    int64_t n_close;     // init: length of the close list
+    // soft-min
+    double sm_m, sm_s;   // running (reference, scaled sum)
+    double sm_L;         // loss of the last forward
+    int64_t sm_nzero;
+};
+
+__device__ __forceinline__ int64_t pair_index(int64_t N, int64_t i, int64_t j) {
+    return i * N - i * (i + 1) / 2 + (j - i - 1);
+}
+
+__device__ __forceinline__ double load_x(const void *X, int dtype, int64_t off) {
+    return dtype == SAP_F64 ? static_cast<const double *>(X)[off]
+                            : static_cast<double>(static_cast<const float *>(X)[off]);
+}
+
+// Butterfly reductions over the 64 lanes of a wavefront.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t w = __shfl_xor(v, o, kWave);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+// lexicographic (r, i, j) minimum
+__device__ __forceinline__ bool lex_less(double r, int32_t i, int32_t j, double r2,
+                                         int32_t i2, int32_t j2) {
+    if (r != r2) return r < r2;
+    if (i != i2) return i < i2;
+    return j < j2;
+}
+
+__device__ __forceinline__ void wave_min_lex(double &r, int32_t &i, int32_t &j) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        double r2 = __shfl_xor(r, o, kWave);
+        int32_t i2 = __shfl_xor(i, o, kWave);
+        int32_t j2 = __shfl_xor(j, o, kWave);
+        if (lex_less(r2, i2, j2, r, i, j)) { r = r2; i = i2; j = j2; }
+    }
+}
+
+}  // namespace sap
+
+// Dispatch a templated launch over the projection width K = 1..16.
+#define SAP_DISPATCH_K(kval, ...)                                           \
+    switch (kval) {                                                          \
+        case 1: { constexpr int K = 1; __VA_ARGS__; } break;                 \
+        case 2: { constexpr int K = 2; __VA_ARGS__; } break;                 \
+        case 3: { constexpr int K = 3; __VA_ARGS__; } break;                 \
+        case 4: { constexpr int K = 4; __VA_ARGS__; } break;                 \
+        case 5: { constexpr int K = 5; __VA_ARGS__; } break;                 \
+        case 6: { constexpr int K = 6; __VA_ARGS__; } break;                 \
+        case 7: { constexpr int K = 7; __VA_ARGS__; } break;                 \
+        case 8: { constexpr int K = 8; __VA_ARGS__; } break;                 \
+        case 9: { constexpr int K = 9; __VA_ARGS__; } break;                 \
+        case 10: { constexpr int K = 10; __VA_ARGS__; } break;               \
+        case 11: { constexpr int K = 11; __VA_ARGS__; } break;               \
+        case 12: { constexpr int K = 12; __VA_ARGS__; } break;               \
+        case 13: { constexpr int K = 13; __VA_ARGS__; } break;               \
+        case 14: { constexpr int K = 14; __VA_ARGS__; } break;               \
+        case 15: { constexpr int K = 15; __VA_ARGS__; } break;               \
+        case 16: { constexpr int K = 16; __VA_ARGS__; } break;               \
+        default: break;                                                      \
+    }

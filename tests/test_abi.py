@@ -1,0 +1,120 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point that
+include/sap.h declares, its structs match the header byte for byte, and
+argument validation rejects bad calls before any HIP call is made."""
+import ctypes as C
+import re
+import subprocess
+from pathlib import Path
+
+import pytest
+
+import paper_1807_03425_amd as sap
+
+ROOT = Path(__file__).resolve().parents[1]
+HEADER = ROOT / "include" / "sap.h"
+
+
+def _declared():
+    txt = HEADER.read_text()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sap_[A-Za-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert "sap_init" in names and "sap_softmin_bwd" in names and len(names) >= 12
+    L = C.CDLL(str(sap.LIB_PATH))
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(sap._SIGS)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text(f"""
+#include <stdio.h>
+#include <stddef.h>
+#include "{HEADER}"
+#define F(T, m) printf("%s.%s %zu\\n", #T, #m, offsetof(T, m));
+int main(void) {{
+  printf("sap_config %zu\\n", sizeof(sap_config));
+  printf("sap_min_result %zu\\n", sizeof(sap_min_result));
+  printf("sap_info_t %zu\\n", sizeof(sap_info_t));
+  F(sap_config, alpha) F(sap_config, close_d) F(sap_config, close_cap)
+  F(sap_min_result, certified) F(sap_min_result, reserved) F(sap_info_t, n_tiles)
+  return 0;
+}}""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(prog)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True,
+                                                        text=True, check=True).stdout.split("\n") if l)
+    assert int(out["sap_config"]) == C.sizeof(sap.sap_config)
+    assert int(out["sap_min_result"]) == C.sizeof(sap.sap_min_result)
+    assert int(out["sap_info_t"]) == C.sizeof(sap.sap_info_t)
+    for key, (cls, field) in {"sap_config.alpha": (sap.sap_config, "alpha"),
+                              "sap_config.close_d": (sap.sap_config, "close_d"),
+                              "sap_config.close_cap": (sap.sap_config, "close_cap"),
+                              "sap_min_result.certified": (sap.sap_min_result, "certified"),
+                              "sap_min_result.reserved": (sap.sap_min_result, "reserved"),
+                              "sap_info_t.n_tiles": (sap.sap_info_t, "n_tiles")}.items():
+        assert int(out[key]) == getattr(cls, field).offset, key
+
+
+def _cfg(**kw):
+    base = dict(N=100, n=10, k=3, dtype=sap.SAP_F64, form=sap.SAP_PLAIN, rule=0,
+                close_cap=0, alpha=0.01, min_len=0.0, close_d=-1.0)
+    base.update(kw)
+    return sap.sap_config(**base)
+
+
+BAD = [
+    ("N<2", dict(N=1), 1),
+    ("n<1", dict(n=0), 1),
+    ("k<1", dict(k=0), 1),
+    ("k>n", dict(k=11), 1),
+    ("k>16", dict(n=40, k=17), 8),
+    ("lds", dict(n=2000, k=8), 8),
+    ("dtype", dict(dtype=7), 1),
+    ("form", dict(form=3), 1),
+    ("rule", dict(rule=2), 1),
+    ("alpha<0", dict(alpha=-0.1), 1),
+    ("alpha>1", dict(alpha=1.5), 1),
+    ("alpha nan", dict(alpha=float("nan")), 1),
+    ("min_len<0", dict(min_len=-1.0), 1),
+    ("min_len inf", dict(min_len=float("inf")), 1),
+    ("close_d nan", dict(close_d=float("nan")), 1),
+    ("close_cap<0", dict(close_cap=-5), 1),
+]
+
+
+@pytest.mark.parametrize("name,kw,status", BAD, ids=[b[0] for b in BAD])
+def test_init_rejects_bad_config_before_any_device_call(name, kw, status):
+    L = sap.lib()
+    h = C.c_void_p(123)
+    fake = C.c_void_p(0x1000)            # never dereferenced: validation comes first
+    st = L.sap_init(C.byref(_cfg(**kw)), fake, 10 if "n" not in kw else max(kw["n"], 1),
+                    fake, None, C.byref(h))
+    assert st == status, (name, st, L.sap_last_error(None))
+    assert h.value is None
+    assert L.sap_last_error(None)
+
+
+def test_init_rejects_null_pointers_and_short_ldx():
+    L = sap.lib()
+    h = C.c_void_p()
+    fake = C.c_void_p(0x1000)
+    assert L.sap_init(None, fake, 10, fake, None, C.byref(h)) == 1
+    assert L.sap_init(C.byref(_cfg()), None, 10, fake, None, C.byref(h)) == 1
+    assert L.sap_init(C.byref(_cfg()), fake, 10, None, None, C.byref(h)) == 1
+    assert L.sap_init(C.byref(_cfg()), fake, 10, fake, None, None) == 1
+    assert L.sap_init(C.byref(_cfg()), fake, 9, fake, None, C.byref(h)) == 1
+    assert b"ldx" in L.sap_last_error(None)
+
+
+def test_null_handle_calls_fail_cleanly():
+    L = sap.lib()
+    r = sap.sap_min_result()
+    assert L.sap_min_secant(None, C.byref(r)) == 1
+    assert L.sap_step(None, None) == 1
+    assert L.sap_run(None, 3, None, None, None) == 1
+    assert L.sap_destroy(None) == 0

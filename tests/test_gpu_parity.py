@@ -1,0 +1,272 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Bars (single-evaluation and single-step parity, compared in lockstep: the
+oracle is fed the GPU's P at every checked iteration, because a trajectory
+that meets a near-tie may legitimately branch):
+  * argmin pair identical unless the oracle's runner-up is within 1e-6 of its
+    minimum; then the GPU pair must score within 1e-6 of the minimum;
+  * min norm within 1e-12 relative plus 2 sqrt(k) n 2^-53 absolute: both
+    sides evaluate the winning pair in FP64 from the same input bytes (the
+    GPU's FP32 coarse pass only selects which pairs to rescore, inside a
+    proven error window), and each FP64 dot product P^T s of a unit secant
+    carries an absolute error of at most about n 2^-53 per component;
+  * updated basis within 1e-12 of the oracle's update from the same P and
+    pair (max abs elementwise).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import sap_inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1807_03425_amd import SapContext, SapError  # noqa: E402
+
+DEV = torch.device("cuda:0")
+MIN_RTOL = 1e-12
+BASIS_TOL = 1e-12
+NEAR_TIE = 1e-6
+
+
+def _ctx(w, form, **kw):
+    X = torch.from_numpy(w.X).to(DEV)
+    return SapContext(X, torch.from_numpy(w.P0), form=form, alpha=w.alpha, **kw), X
+
+
+def min_tol(r, n, k):
+    return MIN_RTOL * r + 2.0 * np.sqrt(k) * n * 2.0 ** -53
+
+
+def _check_eval(Xnp, P, res, tag=""):
+    ref = oracle.min_secant(Xnp, P)
+    tol = min_tol(ref["r_min"], *P.shape)
+    assert res["certified"] == 1, (tag, res)
+    gap = ref["r_second"] - ref["r_min"]
+    if (res["i"], res["j"]) != (ref["i"], ref["j"]):
+        assert gap < NEAR_TIE, (tag, res, ref)
+        r_gpu_pair, _ = oracle.pair_r(Xnp, P, res["i"], res["j"])
+        assert r_gpu_pair <= ref["r_min"] + NEAR_TIE, (tag, res, ref)
+    assert abs(res["min_norm"] - ref["r_min"]) <= tol, (tag, res, ref)
+    return ref
+
+
+def _lockstep(w, form, iters, check_every=1, **kw):
+    ctx, X = _ctx(w, form, **kw)
+    Xnp = w.X
+    for it in range(iters):
+        P = ctx.get_P().cpu().numpy()
+        res = ctx.step(sync=True)
+        if it % check_every == 0 or it == iters - 1:
+            _check_eval(Xnp, P, res, f"{w.name}/{form}/it{it}")
+            s, _ = oracle.unit_secant(Xnp, res["i"], res["j"])
+            P_ref, t_ref = oracle.step(P, s, w.alpha)
+            P_gpu = ctx.get_P().cpu().numpy()
+            assert res["t"] == t_ref, (it, res["t"], t_ref)
+            assert np.abs(P_gpu - P_ref).max() < BASIS_TOL, (it, np.abs(P_gpu - P_ref).max())
+    Pf = ctx.get_P().cpu().numpy()
+    assert oracle.orth_error(Pf) < 1e-12
+    ctx.close()
+
+
+# ------------------------------------------------------------------ small, full lockstep
+
+def test_trig10_plain_fp64_full_run_lockstep():
+    """The paper's Sec. 5 curve (N=200, R^10 -> R^3, FP64), 200 iterations."""
+    _lockstep(sap_inputs.make("trig10"), "plain", 200)
+
+
+@pytest.mark.parametrize("form", ["plain", "fused"])
+def test_trig64_small_lockstep(form):
+    """Harmonics 1..32 curve at N=300 (5 tiles of 64 + a ragged tail)."""
+    _lockstep(sap_inputs.make("trig64", N=300), form, 60)
+
+
+@pytest.mark.parametrize("k", [2, 4, 8])
+def test_blob_small_fused_lockstep(k):
+    _lockstep(sap_inputs.make("blob", N=260, k=k), "fused", 12)
+
+
+def test_hyper_small_fused_lockstep():
+    _lockstep(sap_inputs.make("hyper", N=330), "fused", 12)
+
+
+def test_torus_small_fused_lockstep():
+    _lockstep(sap_inputs.make("torus", N=200), "fused", 8)
+
+
+def test_trig10_fused_fp64_data():
+    _lockstep(sap_inputs.make("trig10", N=150), "fused", 30)
+
+
+# ------------------------------------------------------------------ traces and determinism
+
+@pytest.mark.parametrize("form", ["plain", "fused"])
+def test_run_trace_matches_oracle_until_first_near_tie(form):
+    w = sap_inputs.make("trig10", N=120)
+    iters = 80
+    ctx, X = _ctx(w, form)
+    tr = ctx.run(iters)
+    torch.cuda.synchronize()
+    P_gpu = ctx.get_P().cpu().numpy()
+    P_or, ot = oracle.run(w.X, w.P0, iters)
+    gmin = tr["min"].cpu().numpy()
+    gij = tr["ij"].cpu().numpy()
+    assert np.all(tr["certified"].cpu().numpy() == 1)
+    for it in range(iters + 1):
+        if ot["second"][it] - ot["min"][it] < NEAR_TIE:
+            break
+        assert tuple(gij[it]) == tuple(ot["ij"][it]), it
+        assert abs(gmin[it] - ot["min"][it]) <= 1e-10 * ot["min"][it], it
+    else:
+        assert np.abs(P_gpu - P_or).max() < 1e-9
+    # a second run from the same start reproduces the trace bit for bit
+    ctx2, _ = _ctx(w, form)
+    tr2 = ctx2.run(iters)
+    torch.cuda.synchronize()
+    assert torch.equal(tr2["min"], tr["min"]) and torch.equal(tr2["ij"], tr["ij"])
+    ctx.close(); ctx2.close()
+
+
+def test_set_get_P_roundtrip_and_resume():
+    w = sap_inputs.make("trig64", N=200)
+    ctx, X = _ctx(w, "fused")
+    ctx.run(5)
+    P5 = ctx.get_P()
+    tr_a = ctx.run(7)
+    ctx.set_P(P5)
+    tr_b = ctx.run(7)
+    torch.cuda.synchronize()
+    assert torch.equal(tr_a["min"], tr_b["min"]) and torch.equal(tr_a["ij"], tr_b["ij"])
+    ctx.close()
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_two_points():
+    X = np.array([[0.0, 0.0], [0.6, 0.8]])
+    P = np.array([[1.0], [0.0]])
+    for form in ("plain", "fused"):
+        ctx = SapContext(torch.from_numpy(X).to(DEV), torch.from_numpy(P), form=form)
+        res = ctx.min_secant()
+        assert (res["i"], res["j"]) == (0, 1) and abs(res["min_norm"] - 0.6) < 1e-15
+        ctx.close()
+
+
+@pytest.mark.parametrize("N", [65, 127, 129])
+@pytest.mark.parametrize("form", ["plain", "fused"])
+def test_ragged_tails(N, form):
+    w = sap_inputs.make("trig64", N=N)
+    ctx, X = _ctx(w, form)
+    _check_eval(w.X, w.P0, ctx.min_secant(), f"N={N}")
+    ctx.close()
+
+
+@pytest.mark.parametrize("form", ["plain", "fused"])
+def test_duplicates_and_length_threshold(form):
+    w = sap_inputs.make("trig10", N=90)
+    X = w.X.copy()
+    X[10] = X[3]
+    X[50] = X[3]
+    X[77] = X[20]
+    for ml in (0.0, 0.7):
+        ctx = SapContext(torch.from_numpy(X).to(DEV), torch.from_numpy(w.P0), form=form, min_len=ml)
+        res = ctx.min_secant()
+        ref = oracle.min_secant(X, w.P0, min_len=ml)
+        info = ctx.info()
+        assert info["n_pairs"] == ref["n_pairs"] and info["n_dropped"] == ref["n_dropped"]
+        assert (res["i"], res["j"]) == (ref["i"], ref["j"])
+        assert abs(res["min_norm"] - ref["r_min"]) <= min_tol(ref["r_min"], *w.P0.shape)
+        ctx.close()
+
+
+def test_k_equals_n_and_k_one():
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((70, 5))
+    for k in (5, 1):
+        P = sap_inputs.random_orthonormal(rng, 5, k)
+        for form in ("plain", "fused"):
+            ctx = SapContext(torch.from_numpy(X).to(DEV), torch.from_numpy(P), form=form)
+            res = ctx.min_secant()
+            if k == 5:
+                assert abs(res["min_norm"] - 1.0) < 1e-13
+            else:
+                _check_eval(X, P, res, f"k=1/{form}")
+            ctx.close()
+
+
+def test_affine_plane_min_is_one():
+    rng = np.random.default_rng(11)
+    A = sap_inputs.random_orthonormal(rng, 12, 3)
+    X = (rng.standard_normal((150, 3)) @ A.T + 0.5).astype(np.float32)
+    for form in ("plain", "fused"):
+        ctx = SapContext(torch.from_numpy(X).to(DEV), torch.from_numpy(A), form=form)
+        res = ctx.min_secant()
+        ref = oracle.min_secant(X, A)
+        assert abs(res["min_norm"] - ref["r_min"]) <= min_tol(1.0, *A.shape)
+        assert abs(res["min_norm"] - 1.0) < 1e-6
+        ctx.close()
+
+
+def test_errors_reported():
+    w = sap_inputs.make("trig10", N=50)
+    X = torch.from_numpy(w.X).to(DEV)
+    with pytest.raises(SapError) as e:
+        SapContext(torch.zeros((5, 4), dtype=torch.float64, device=DEV),
+                   torch.from_numpy(np.eye(4)[:, :2]))
+    assert e.value.status == 3                       # no pairs
+    Xbad = X.clone(); Xbad[7, 2] = float("nan")
+    with pytest.raises(SapError) as e:
+        SapContext(Xbad, torch.from_numpy(w.P0))
+    assert e.value.status == 2                       # nonfinite
+    with pytest.raises(SapError) as e:
+        SapContext(X, torch.from_numpy(w.P0 * 1.01))
+    assert e.value.status == 6                       # not orthonormal
+    ctx = SapContext(X, torch.from_numpy(w.P0))
+    with pytest.raises(SapError):
+        ctx.set_P(torch.from_numpy(w.P0 * 2.0))
+    assert ctx.min_secant()["certified"] == 1        # the handle stays usable
+    ctx.close()
+
+
+# ------------------------------------------------------------------ full-size workloads
+
+def test_trig64_full_size_plain_and_fused_agree_with_oracle():
+    """The 4,000-point, 8.0e6-secant workload in both forms: lockstep for a few
+    iterations from the seeded start (oracle on all 8e6 pairs each time)."""
+    w = sap_inputs.make("trig64")
+    for form in ("plain", "fused"):
+        ctx, X = _ctx(w, form)
+        for it in range(3):
+            P = ctx.get_P().cpu().numpy()
+            res = ctx.step(sync=True)
+            _check_eval(w.X, P, res, f"full/{form}/{it}")
+        ctx.close()
+
+
+@pytest.mark.parametrize("name,k", [("blob", 2), ("blob", 8), ("hyper", 10), ("torus", 16)])
+def test_large_workloads_sampled(name, k):
+    """Full-size fused runs: the reported pair's FP64 value is recomputed by
+    the oracle, and a random sample of pairs evaluated by the oracle never
+    beats the reported minimum."""
+    w = sap_inputs.make(name, k=k)
+    ctx, X = _ctx(w, "fused")
+    ctx.run(3)
+    P = ctx.get_P().cpu().numpy()
+    res = ctx.min_secant()
+    assert res["certified"] == 1
+    r_pair, _ = oracle.pair_r(w.X, P, res["i"], res["j"])
+    assert abs(r_pair - res["min_norm"]) <= min_tol(r_pair, *P.shape)
+    rng = np.random.default_rng(0)
+    N = w.N
+    ii = rng.integers(0, N, 20000)
+    jj = rng.integers(0, N, 20000)
+    keep = ii != jj
+    r = oracle.pairs_r(w.X, P, np.stack([ii[keep], jj[keep]], axis=1))
+    r = r[np.isfinite(r)]
+    assert r.min() >= res["min_norm"] - 1e-12
+    ctx.close()
