@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Projected secants/s and ms per SAP iteration, fused vs plain.
+
+Workload: the trigonometric moment curve with harmonics 1..32 (n = 64),
+N = 4,000 points (7,998,000 unit secants), FP32 input, projection to k = 6
+from the seeded random orthonormal start, alpha = 0.01 -- the curve of the
+paper's Sec. 5 at the scale where both forms of the pass fit one GPU.
+
+A timed step is one SAP iteration: evaluate every secant, reduce to the
+FP64-rescored min/argmin, apply the update.  `value` is the fused form's
+secants/s (kept pairs x timed iterations / wall time of the timed region,
+inputs resident in HBM); the plain form is reported beside it.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: lane-instructions/s
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_form(torch, ctx, steps, warmup, prof_steps):
+    dev = torch.device("cuda:0")
+    m = steps + 1
+    out = dict(min=torch.empty(m, dtype=torch.float64, device=dev),
+               ij=torch.empty((m, 2), dtype=torch.int64, device=dev),
+               certified=torch.empty(m, dtype=torch.int32, device=dev))
+    P0 = ctx.get_P()
+    if warmup:
+        ctx.run(warmup)
+    ctx.set_P(P0)                                   # timed run starts at the seeded P0
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    ctx.run(steps, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    P_final = ctx.get_P().cpu().numpy()
+    # per-kernel durations, HIP events on the library's stream, same work
+    ctx.set_P(P0)
+    ctx.profile(True)
+    ctx.run(prof_steps)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    return dict(wall_s=wall, event_ms=ev_ms, trace={k: v.cpu().numpy() for k, v in out.items()},
+                P_final=P_final, profile=prof)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500, help="timed SAP iterations per form")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--forms", default="fused,plain")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="budget of the FP64 CPU oracle baseline (0 disables it)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU: this build runs the SAP pass on a single "
+              f"MI355X and has no multi-GPU path (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE={world}).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import sap_inputs
+    from paper_1807_03425_amd import SapContext
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    w = sap_inputs.make("trig64")
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(w.X).to(dev)
+    P0 = torch.from_numpy(w.P0)
+    forms = [f for f in args.forms.split(",") if f]
+    res = {}
+    for form in forms:
+        t = time.perf_counter()
+        ctx = SapContext(X, P0, form=form, alpha=w.alpha)
+        torch.cuda.synchronize()
+        init_s = time.perf_counter() - t
+        info = ctx.info()
+        log(f"{form}: init {init_s:.3f}s, pairs {info['n_pairs']}, close {info['n_close']}, "
+            f"e_abs {info['e_abs']:.3g}")
+        r = time_form(torch, ctx, args.steps, args.warmup, min(args.steps, 200))
+        r.update(info=info, init_s=init_s)
+        ms = r["event_ms"] / args.steps
+        log(f"{form}: {args.steps} iterations in {r['event_ms']:.2f} ms (events), "
+            f"{r['wall_s']*1e3:.2f} ms (wall) -> {ms*1e3:.1f} us/iter")
+        res[form] = r
+        ctx.close()
+        del ctx
+        torch.cuda.synchronize()
+
+    def summary(form):
+        r = res[form]
+        info = r["info"]
+        t = max(r["wall_s"], r["event_ms"] / 1e3)
+        pairs = info["n_pairs"]
+        prof = r["profile"]
+        p = prof["pass"]
+        avg_pass_s = p["ms"] / max(p["launches"], 1) / 1e3
+        per_iter_ms = {k: v["ms"] / max(v["launches"], 1) for k, v in prof.items() if v["launches"]}
+        if form == "fused":
+            bytes_launch = 4 * pairs                       # one FP32 1/d^2 per pair
+            valu = (2 * w.k + 2) * pairs                   # lane-instructions per launch
+        else:
+            bytes_launch = 4 * w.n * pairs                 # n FP32 components per stored secant
+            valu = (w.n * w.k + w.k) * pairs
+        return dict(
+            secants_per_s=pairs * args.steps / t,
+            ms_per_iter=t * 1e3 / args.steps,
+            init_s=r["init_s"],
+            certified_frac=float(np.mean(r["trace"]["certified"] == 1)),
+            kernel_ms_per_launch=per_iter_ms,
+            pass_kernel=dict(avg_us=avg_pass_s * 1e6, bytes_per_launch=bytes_launch,
+                             gbs=bytes_launch / avg_pass_s / 1e9 if avg_pass_s > 0 else None,
+                             valu_lane_instr_per_launch=valu,
+                             valu_frac=valu / avg_pass_s / VALU_LANE_OPS if avg_pass_s > 0 else None),
+            n_close=info["n_close"], e_abs=info["e_abs"],
+        )
+
+    sums = {f: summary(f) for f in res}
+    head = "fused" if "fused" in sums else forms[0]
+    hs = sums[head]
+    pk = hs["pass_kernel"]
+    roofline = dict(bound="hbm", achieved=pk["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=(pk["gbs"] / HBM_PEAK_GBS) if pk["gbs"] else None, traffic=None,
+                    kernel=f"k_pair_{head}", bytes_per_launch=pk["bytes_per_launch"],
+                    avg_launch_us=pk["avg_us"], valu_frac=pk["valu_frac"])
+
+    accuracy = {}
+    if "fused" in res and "plain" in res:
+        a, b = res["fused"]["trace"], res["plain"]["trace"]
+        same = a["ij"] == b["ij"]
+        first_diff = int(np.argmin(same.all(axis=1))) if not same.all() else None
+        upto = first_diff if first_diff is not None else len(a["min"])
+        accuracy["fused_vs_plain"] = dict(
+            identical_argmin_trace=first_diff is None, first_divergence=first_diff,
+            max_abs_dmin_before_divergence=float(np.max(np.abs(a["min"][:upto] - b["min"][:upto])))
+            if upto else None)
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        import oracle        # CPU baseline leg: the FP64 oracle, untuned
+        cores = oracle.num_threads()
+        log(f"cpu baseline: FP64 oracle on {cores} threads, budget {args.cpu_seconds}s")
+        P = w.P0.copy()
+        it = 0
+        t0 = time.perf_counter()
+        while True:
+            m = oracle.min_secant(w.X, P)
+            s, _ = oracle.unit_secant(w.X, m["i"], m["j"])
+            P, _ = oracle.step(P, s, w.alpha)
+            it += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t0
+        cpu = dict(value=m["n_pairs"] * it / dt, unit="secants/s", cores=cores, kind="oracle",
+                   sample=f"{it} full SAP iterations (all {m['n_pairs']} secants each, "
+                          f"FP64, explicit unit secants) of the same workload from the seeded start",
+                   ms_per_iter=dt * 1e3 / it)
+        log(f"cpu baseline: {it} iterations in {dt:.1f}s")
+        # accuracy of the timed GPU runs: the oracle scores each form's final P
+        for form, r in res.items():
+            ref = oracle.min_secant(w.X, r["P_final"])
+            gmin, gij = r["trace"]["min"][-1], tuple(r["trace"]["ij"][-1])
+            accuracy[form] = dict(
+                final_min_gpu=float(gmin), final_min_oracle=ref["r_min"],
+                rel_err=abs(gmin - ref["r_min"]) / ref["r_min"],
+                argmin_match=gij == (ref["i"], ref["j"]),
+                oracle_gap_to_runner_up=ref["r_second"] - ref["r_min"])
+
+    line = dict(
+        metric="projected secants/sec + ms per SAP iteration, fused vs plain at stated accuracy",
+        value=hs["secants_per_s"], unit="secants/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=hs["ms_per_iter"], higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f32",
+        data="synthetic",
+        config=dict(workload="trig moment curve, harmonics 1..32 (n=64), N=4000, FP32, k=6, "
+                             "alpha=0.01, seeded random orthonormal start",
+                    form=head, pairs=res[head]["info"]["n_pairs"],
+                    arithmetic="FP32 coarse pass; FP64 GEMM (fused), FP64 rescoring and update"),
+        roofline=roofline, cpu_baseline=cpu, forms=sums, accuracy=accuracy,
+    )
+    if "plain" in sums:
+        pp = sums["plain"]["pass_kernel"]
+        line["roofline_plain"] = dict(bound="hbm", achieved=pp["gbs"], peak=HBM_PEAK_GBS,
+                                      unit="GB/s", frac=pp["gbs"] / HBM_PEAK_GBS if pp["gbs"] else None,
+                                      traffic=None, kernel="k_pair_plain",
+                                      bytes_per_launch=pp["bytes_per_launch"],
+                                      avg_launch_us=pp["avg_us"])
+        if "fused" in sums:
+            line["fused_over_plain"] = sums["fused"]["secants_per_s"] / sums["plain"]["secants_per_s"]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

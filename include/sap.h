@@ -167,6 +167,21 @@ sap_status sap_softmin_fwd(sap_handle h, const float *P, double tau,
 sap_status sap_softmin_bwd(sap_handle h, const float *P, double tau,
                            const float *grad_loss, float *dP);
 
+/* Per-kernel timing of the iteration, for roofline reporting.  While enabled,
+ * every kernel launched by sap_min_secant / sap_step / sap_run is bracketed
+ * by a pair of HIP events on the handle's stream (the work itself is
+ * unchanged; the events add a small gap between launches).  sap_profile_read
+ * synchronises, returns the summed durations and launch counts since the
+ * last read, and restarts the accumulation.
+ * Slots: 0 = Y GEMM (fused), 1 = pair pass, 2 = FP64 rescoring, 3 = tail. */
+typedef struct {
+    double ms[4];
+    int64_t launches[4];
+} sap_profile_t;
+
+sap_status sap_profile_enable(sap_handle h, int32_t on);
+sap_status sap_profile_read(sap_handle h, sap_profile_t *out);
+
 /* Free everything the handle owns.  NULL is accepted. */
 sap_status sap_destroy(sap_handle h);
 

@@ -56,6 +56,12 @@ class sap_info_t(C.Structure):
                 ("device_bytes", C.c_int64), ("n_tiles", C.c_int64)]
 
 
+class sap_profile_t(C.Structure):
+    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
+
+
+PROFILE_SLOTS = ("gemm", "pass", "rescore", "tail")
+
 _lib: Optional[C.CDLL] = None
 
 # name -> (restype, argtypes)
@@ -71,6 +77,8 @@ _SIGS = {
     "sap_info": (C.c_int, [C.c_void_p, C.POINTER(sap_info_t)]),
     "sap_softmin_fwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
     "sap_softmin_bwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
+    "sap_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "sap_profile_read": (C.c_int, [C.c_void_p, C.POINTER(sap_profile_t)]),
     "sap_destroy": (C.c_int, [C.c_void_p]),
     "sap_last_error": (C.c_char_p, [C.c_void_p]),
 }
@@ -220,6 +228,16 @@ class SapContext:
         _check(lib().sap_info(self.handle, C.byref(r)), self.handle)
         return {f: getattr(r, f) for f, _ in sap_info_t._fields_}
 
+    # -- per-kernel timing
+    def profile(self, on: bool = True):
+        _check(lib().sap_profile_enable(self.handle, 1 if on else 0), self.handle)
+
+    def profile_read(self) -> dict:
+        r = sap_profile_t()
+        _check(lib().sap_profile_read(self.handle, C.byref(r)), self.handle)
+        return {name: dict(ms=r.ms[i], launches=r.launches[i])
+                for i, name in enumerate(PROFILE_SLOTS)}
+
     # -- soft-min
     def softmin_fwd(self, P, tau: float):
         import torch
@@ -273,4 +291,4 @@ class _LazySoftMin:
 SoftMinSecant = _LazySoftMin()
 
 __all__ = ["SapContext", "SoftMinSecant", "SapError", "lib", "LIB_PATH", "sap_config",
-           "sap_min_result", "sap_info_t"]
+           "sap_min_result", "sap_info_t", "sap_profile_t"]

@@ -56,6 +56,12 @@ struct sap_ctx {
     int64_t kept = 0, dropped = 0;
     int64_t dev_bytes = 0;
     std::vector<void *> allocs;
+
+    // per-kernel timing (sap_profile_enable)
+    struct Mark { hipEvent_t a, b; int slot; };
+    bool prof_on = false;
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> ev_pool;
 };
 
 static thread_local std::string g_tls_err;
@@ -346,21 +352,50 @@ static sap_status init_fused(sap_ctx *h) {
 
 // ---------------------------------------------------------------- iteration
 
+static sap_status ev_get(sap_ctx *h, hipEvent_t *e) {
+    if (!h->ev_pool.empty()) { *e = h->ev_pool.back(); h->ev_pool.pop_back(); return SAP_OK; }
+    SAP_HIP(h, hipEventCreate(e));
+    return SAP_OK;
+}
+
+// Bracket the next launch with events when profiling is on.
+static sap_status prof_begin(sap_ctx *h, hipEvent_t *e) {
+    if (!h->prof_on) return SAP_OK;
+    SAP_TRY(ev_get(h, e));
+    SAP_HIP(h, hipEventRecord(*e, h->stream));
+    return SAP_OK;
+}
+
+static sap_status prof_end(sap_ctx *h, hipEvent_t a, int slot) {
+    if (!h->prof_on) return SAP_OK;
+    hipEvent_t b;
+    SAP_TRY(ev_get(h, &b));
+    SAP_HIP(h, hipEventRecord(b, h->stream));
+    h->marks.push_back(sap_ctx::Mark{a, b, slot});
+    return SAP_OK;
+}
+
 // Enqueue one evaluation (+ update when do_step).
 static sap_status enqueue_eval(sap_ctx *h, int do_step, double *tr_min, int64_t *tr_ij,
                                int32_t *tr_cert, int it) {
     const int K = h->k;
     const bool f64 = h->cfg.dtype == SAP_F64;
     uint32_t *gmin = &h->d_st->gmin;
+    hipEvent_t ev = nullptr;
     if (h->cfg.form == SAP_FUSED) {
+        SAP_TRY(prof_begin(h, &ev));
         hipLaunchKernelGGL(k_gemm_y, dim3((unsigned)(h->Npad / 64)), dim3(256), 0, h->stream, h->X,
                            h->cfg.dtype, h->ldx, h->N, h->n, h->k, h->d_mu, h->d_P64t, h->d_Y,
                            h->kp, h->Npad);
         SAP_LAUNCHED(h, "k_gemm_y");
+        SAP_TRY(prof_end(h, ev, 0));
+        SAP_TRY(prof_begin(h, &ev));
         SAP_DISPATCH_K(K, hipLaunchKernelGGL(k_pair_fused<K>, dim3(h->pass_grid), dim3(kPairBlock),
                                              0, h->stream, h->d_Y, h->kp, h->d_invd2, h->d_tiles,
                                              h->ntiles, h->d_tmin, gmin));
         SAP_LAUNCHED(h, "k_pair_fused");
+        SAP_TRY(prof_end(h, ev, 1));
+        SAP_TRY(prof_begin(h, &ev));
         if (f64) {
             SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_rescore_fused<K, double>), dim3(h->rescore_grid),
                                                  dim3(kPairBlock), 0, h->stream, h->d_Y, h->kp,
@@ -377,7 +412,9 @@ static sap_status enqueue_eval(sap_ctx *h, int do_step, double *tr_min, int64_t 
                                                  h->d_part));
         }
         SAP_LAUNCHED(h, "k_rescore_fused");
+        SAP_TRY(prof_end(h, ev, 2));
     } else {
+        SAP_TRY(prof_begin(h, &ev));
         if (f64) {
             const double *S = static_cast<const double *>(h->d_S);
             const double *Pr = static_cast<const double *>(h->d_Pr);
@@ -385,6 +422,8 @@ static sap_status enqueue_eval(sap_ctx *h, int do_step, double *tr_min, int64_t 
                                                  dim3(kPairBlock), 0, h->stream, S, h->pcols, h->n,
                                                  Pr, h->nchunks, h->d_tmin, gmin));
             SAP_LAUNCHED(h, "k_pair_plain");
+            SAP_TRY(prof_end(h, ev, 1));
+            SAP_TRY(prof_begin(h, &ev));
             SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_rescore_plain<K, double>), dim3(h->rescore_grid),
                                                  dim3(kPairBlock), 0, h->stream, S, h->pcols, h->n,
                                                  Pr, h->nchunks, h->d_tmin, gmin, h->e_abs, h->e_rel,
@@ -397,6 +436,8 @@ static sap_status enqueue_eval(sap_ctx *h, int do_step, double *tr_min, int64_t 
                                                  dim3(kPairBlock), 0, h->stream, S, h->pcols, h->n,
                                                  Pr, h->nchunks, h->d_tmin, gmin));
             SAP_LAUNCHED(h, "k_pair_plain");
+            SAP_TRY(prof_end(h, ev, 1));
+            SAP_TRY(prof_begin(h, &ev));
             SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_rescore_plain<K, float>), dim3(h->rescore_grid),
                                                  dim3(kPairBlock), 0, h->stream, S, h->pcols, h->n,
                                                  Pr, h->nchunks, h->d_tmin, gmin, h->e_abs, h->e_rel,
@@ -404,7 +445,9 @@ static sap_status enqueue_eval(sap_ctx *h, int do_step, double *tr_min, int64_t 
                                                  h->d_P64t, h->d_part));
         }
         SAP_LAUNCHED(h, "k_rescore_plain");
+        SAP_TRY(prof_end(h, ev, 2));
     }
+    SAP_TRY(prof_begin(h, &ev));
     const int pr_kind = h->cfg.form == SAP_PLAIN ? (f64 ? 2 : 1) : 0;
     if (f64)
         hipLaunchKernelGGL(k_tail<double>, dim3(1), dim3(64), h->tail_lds, h->stream, h->d_part,
@@ -419,6 +462,7 @@ static sap_status enqueue_eval(sap_ctx *h, int do_step, double *tr_min, int64_t 
                            h->d_Pr, pr_kind, h->cfg.alpha, h->cfg.rule, do_step, h->d_res, tr_min,
                            tr_ij, tr_cert, it);
     SAP_LAUNCHED(h, "k_tail");
+    SAP_TRY(prof_end(h, ev, 3));
     return SAP_OK;
 }
 
@@ -448,6 +492,8 @@ static sap_status usable(sap_ctx *h) {
 
 static void destroy_ctx(sap_ctx *h) {
     if (!h) return;
+    for (auto &m : h->marks) { (void)hipEventDestroy(m.a); (void)hipEventDestroy(m.b); }
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     for (void *p : h->allocs) (void)hipFree(p);
     delete h;
 }
@@ -579,6 +625,29 @@ sap_status sap_softmin_bwd(sap_handle h, const float *P, double tau, const float
     SAP_TRY(usable(h));
     (void)P; (void)tau; (void)grad_loss; (void)dP;
     return fail(h, SAP_ERR_UNSUPPORTED, "soft-min is not available in this build");
+}
+
+sap_status sap_profile_enable(sap_handle h, int32_t on) {
+    SAP_TRY(usable(h));
+    h->prof_on = on != 0;
+    return SAP_OK;
+}
+
+sap_status sap_profile_read(sap_handle h, sap_profile_t *out) {
+    SAP_TRY(usable(h));
+    if (!out) return fail(h, SAP_ERR_INVALID_ARG, "null profile pointer");
+    SAP_HIP(h, hipStreamSynchronize(h->stream));
+    std::memset(out, 0, sizeof *out);
+    for (auto &m : h->marks) {
+        float ms = 0.0f;
+        SAP_HIP(h, hipEventElapsedTime(&ms, m.a, m.b));
+        out->ms[m.slot] += ms;
+        out->launches[m.slot] += 1;
+        h->ev_pool.push_back(m.a);
+        h->ev_pool.push_back(m.b);
+    }
+    h->marks.clear();
+    return SAP_OK;
 }
 
 sap_status sap_destroy(sap_handle h) {
