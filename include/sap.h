@@ -173,7 +173,9 @@ sap_status sap_softmin_bwd(sap_handle h, const float *P, double tau,
  * unchanged; the events add a small gap between launches).  sap_profile_read
  * synchronises, returns the summed durations and launch counts since the
  * last read, and restarts the accumulation.
- * Slots: 0 = Y GEMM (fused), 1 = pair pass, 2 = FP64 rescoring, 3 = tail. */
+ * Slots: 0 = Y GEMM (fused form), 1 = pair pass (with the fused form's FP64
+ * short pairs), 2 = selection: window, FP64 rescoring, record and update;
+ * 3 is unused. */
 typedef struct {
     double ms[4];
     int64_t launches[4];

@@ -60,7 +60,7 @@ class sap_profile_t(C.Structure):
     _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
 
 
-PROFILE_SLOTS = ("gemm", "pass", "rescore", "tail")
+PROFILE_SLOTS = ("gemm", "pass", "select", "unused")
 
 _lib: Optional[C.CDLL] = None
 

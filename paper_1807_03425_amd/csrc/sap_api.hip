@@ -36,6 +36,7 @@ struct sap_ctx {
     float4 *d_invd2 = nullptr;
     float *d_Y = nullptr;
     int2 *d_close = nullptr;
+    double *d_cdiff = nullptr, *d_cd = nullptr;   // short pairs: x_i - x_j (one row each), ||.||
 
     // plain
     void *d_S = nullptr;
@@ -44,12 +45,14 @@ struct sap_ctx {
 
     // common
     double *d_P64t = nullptr;
+    double *d_P64r = nullptr;
     double *d_mu = nullptr;
     uint32_t *d_tmin = nullptr;
     DevState *d_st = nullptr;
     Partial *d_part = nullptr;
     DevResult *d_res = nullptr;
-    int pass_grid = 0, rescore_grid = 0;
+    int pass_grid = 0, short_grid = 0, short_group = 8;
+    uint32_t *d_blk = nullptr;   // per pass block minimum
     size_t tail_lds = 0;
 
     double radius = 0, close_d = 0, e_abs = 0, e_rel = 0;
@@ -178,15 +181,16 @@ static sap_status load_P(sap_ctx *h, const double *P_dev) {
         for (int q = 0; q < k; ++q) Pt[(size_t)q * n + l] = P[(size_t)l * k + q];
     SAP_HIP(h, hipMemcpyAsync(h->d_P64t, Pt.data(), sizeof(double) * n * k, hipMemcpyHostToDevice,
                               h->stream));
-    if (h->cfg.form == SAP_PLAIN) {
+    {
         const int blocks = (int)ceil_div((int64_t)n * k, 256);
-        if (h->cfg.dtype == SAP_F32)
-            hipLaunchKernelGGL(k_write_pass_P<float>, dim3(blocks), dim3(256), 0, h->stream,
-                               h->d_P64t, n, k, static_cast<float *>(h->d_Pr));
+        if (h->cfg.form == SAP_PLAIN && h->cfg.dtype == SAP_F64)
+            hipLaunchKernelGGL(k_write_P_copies<double>, dim3(blocks), dim3(256), 0, h->stream,
+                               h->d_P64t, n, k, h->d_P64r, static_cast<double *>(h->d_Pr));
         else
-            hipLaunchKernelGGL(k_write_pass_P<double>, dim3(blocks), dim3(256), 0, h->stream,
-                               h->d_P64t, n, k, static_cast<double *>(h->d_Pr));
-        SAP_LAUNCHED(h, "k_write_pass_P");
+            hipLaunchKernelGGL(k_write_P_copies<float>, dim3(blocks), dim3(256), 0, h->stream,
+                               h->d_P64t, n, k, h->d_P64r,
+                               h->cfg.form == SAP_PLAIN ? static_cast<float *>(h->d_Pr) : nullptr);
+        SAP_LAUNCHED(h, "k_write_P_copies");
     }
     SAP_HIP(h, hipStreamSynchronize(h->stream));
     return SAP_OK;
@@ -265,7 +269,7 @@ static sap_status init_fused(sap_ctx *h) {
     SAP_TRY(dalloc(h, &h->d_tiles, sizeof(int2) * h->ntiles));
     SAP_TRY(dalloc(h, &h->d_invd2, sizeof(float) * (size_t)h->ntiles * kTileElems));
     SAP_TRY(dalloc(h, &h->d_Y, sizeof(float) * (size_t)h->Npad * h->kp));
-    SAP_TRY(dalloc(h, &h->d_tmin, sizeof(uint32_t) * h->ntiles));
+    SAP_TRY(dalloc(h, &h->d_tmin, sizeof(uint32_t) * 4 * h->ntiles));
     SAP_HIP(h, hipMemcpyAsync(h->d_tiles, tiles.data(), sizeof(int2) * h->ntiles,
                               hipMemcpyHostToDevice, h->stream));
 
@@ -320,17 +324,19 @@ static sap_status init_fused(sap_ctx *h) {
     }
     const float thr = ladder[msel];
     const int64_t want = (int64_t)above[msel];
-    if (want > 0) {
-        SAP_TRY(dalloc(h, &h->d_close, sizeof(int2) * want));
+    if (want > 0) SAP_TRY(dalloc(h, &h->d_close, sizeof(int2) * want));
+    {
         unsigned long long *d_count = reinterpret_cast<unsigned long long *>(&h->d_st->n_close);
         hipLaunchKernelGGL(k_mark_close, dim3(grid), dim3(256), 0, h->stream, h->d_invd2, h->d_tiles,
-                           h->ntiles, thr, h->d_close, want, d_count);
+                           h->ntiles, thr, h->d_close, want, d_count, &h->d_st->keep_max);
         SAP_LAUNCHED(h, "k_mark_close");
         SAP_HIP(h, hipMemcpyAsync(&st, h->d_st, sizeof st, hipMemcpyDeviceToHost, h->stream));
         SAP_HIP(h, hipStreamSynchronize(h->stream));
         if (st.n_close != want)
             return fail(h, SAP_ERR_DEVICE, "short-pair count mismatch (%lld vs %lld)",
                         (long long)st.n_close, (long long)want);
+    }
+    if (want > 0) {
         // deterministic order: sort by (i, j)
         std::vector<int2> lst((size_t)want);
         SAP_HIP(h, hipMemcpyAsync(lst.data(), h->d_close, sizeof(int2) * want, hipMemcpyDeviceToHost, h->stream));
@@ -339,14 +345,33 @@ static sap_status init_fused(sap_ctx *h) {
             return a.x != b.x ? a.x < b.x : a.y < b.y;
         });
         SAP_HIP(h, hipMemcpyAsync(h->d_close, lst.data(), sizeof(int2) * want, hipMemcpyHostToDevice, h->stream));
+        SAP_TRY(dalloc(h, &h->d_cdiff, sizeof(double) * (size_t)h->n * want));
+        SAP_TRY(dalloc(h, &h->d_cd, sizeof(double) * (size_t)want));
+        const unsigned gblk = (unsigned)ceil_div(want, 256);
+        if (h->cfg.dtype == SAP_F64)
+            hipLaunchKernelGGL(k_short_diffs<double>, dim3(gblk), dim3(256), 0, h->stream,
+                               static_cast<const double *>(h->X), h->ldx, h->n, h->d_close, want,
+                               h->d_cdiff, h->d_cd);
+        else
+            hipLaunchKernelGGL(k_short_diffs<float>, dim3(gblk), dim3(256), 0, h->stream,
+                               static_cast<const float *>(h->X), h->ldx, h->n, h->d_close, want,
+                               h->d_cdiff, h->d_cd);
+        SAP_LAUNCHED(h, "k_short_diffs");
     }
     h->nclose = want;
-    // non-close pairs satisfy fl32(1/d^2) <= thr, hence d >= 1/sqrt(thr (1 + 2^-22))
-    const double Deff = 1.0 / std::sqrt((double)thr * (1.0 + std::ldexp(1.0, -22)));
+    // every pair left to the coarse pass has fl32(1/d^2) <= w_max, hence
+    // d >= 1/sqrt(w_max (1 + 2^-22)); no such pair: no coarse bound needed
+    float wmax;
+    std::memcpy(&wmax, &st.keep_max, sizeof wmax);
     h->close_d = dtarget * std::pow(2.0, -msel / 4.0);
-    h->e_abs = 2.0 * delta / Deff;
+    h->e_abs = st.keep_max ? 2.0 * delta * std::sqrt((double)wmax * (1.0 + std::ldexp(1.0, -22))) : 0.0;
     h->e_rel = (h->k + 4) * kU32;
-    h->pass_grid = (int)std::min<int64_t>(ceil_div(h->ntiles, 4), 2048);
+    h->pass_grid = (int)std::min<int64_t>(ceil_div(2 * h->ntiles, 4), 8192);   // 4 half-tiles per block
+    h->short_group = 8;
+    while (h->short_group < 64 && h->short_group * 8 < h->n) h->short_group *= 2;
+    h->short_grid = h->nclose > 0
+                        ? (int)std::min<int64_t>(ceil_div(h->nclose * h->short_group, kPairBlock), 1024)
+                        : 0;
     return SAP_OK;
 }
 
@@ -375,95 +400,96 @@ static sap_status prof_end(sap_ctx *h, hipEvent_t a, int slot) {
     return SAP_OK;
 }
 
+template <typename TX>
+static SweepArgs<TX> sweep_args(sap_ctx *h, double *tr_min, int64_t *tr_ij, int32_t *tr_cert,
+                                int it) {
+    SweepArgs<TX> a{};
+    a.Y = h->d_Y;
+    a.kp = h->kp;
+    a.invd2 = h->d_invd2;
+    a.tiles = h->d_tiles;
+    a.nhalf = 2 * h->ntiles;
+    a.nb = h->nb;
+    a.S = static_cast<const TX *>(h->d_S);
+    a.pcols = h->pcols;
+    a.Pr = static_cast<const TX *>(h->d_Pr);
+    a.nchunks = h->nchunks;
+    a.n = h->n;
+    a.npass = h->pass_grid;
+    a.unit_min = h->d_tmin;
+    a.blk_min = h->d_blk;
+    a.close = h->d_close;
+    a.cdiff = h->d_cdiff;
+    a.cd = h->d_cd;
+    a.nclose = h->nclose;
+    a.group = h->short_group;
+    a.spart = h->d_part;
+    a.e_abs = h->e_abs;
+    a.e_rel = h->e_rel;
+    a.X = static_cast<const TX *>(h->X);
+    a.ldx = h->ldx;
+    a.N = h->N;
+    a.P64t = h->d_P64t;
+    a.gmin_out = &h->d_st->gmin;
+    a.res = h->d_res;
+    a.tr_min = tr_min;
+    a.tr_ij = tr_ij;
+    a.tr_cert = tr_cert;
+    a.it = it;
+    return a;
+}
+
 // Enqueue one evaluation (+ update when do_step).
+template <typename TX>
+static sap_status launch_iteration(sap_ctx *h, int do_step, double *tr_min, int64_t *tr_ij,
+                                   int32_t *tr_cert, int it) {
+    const int K = h->k;
+    const bool fused = h->cfg.form == SAP_FUSED;
+    hipEvent_t ev = nullptr;
+    const SweepArgs<TX> a = sweep_args<TX>(h, tr_min, tr_ij, tr_cert, it);
+    const int nshort = fused ? h->short_grid : 0;
+    if (fused) {
+        const int gemm_blocks = (int)(h->Npad / 64);
+        SAP_TRY(prof_begin(h, &ev));
+        SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_prep<K, TX>), dim3((unsigned)(gemm_blocks + nshort)),
+                                             dim3(kPairBlock), 0, h->stream, a, h->d_mu, h->d_Y,
+                                             h->Npad, gemm_blocks));
+        SAP_LAUNCHED(h, "k_prep");
+        SAP_TRY(prof_end(h, ev, 0));
+    }
+    const dim3 grid((unsigned)h->pass_grid);
+    SAP_TRY(prof_begin(h, &ev));
+    if (fused) {
+        SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_pass<K, TX, true>), grid, dim3(kPairBlock), 0,
+                                             h->stream, a));
+    } else {
+        SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_pass<K, TX, false>), grid, dim3(kPairBlock), 0,
+                                             h->stream, a));
+    }
+    SAP_LAUNCHED(h, "k_pass");
+    SAP_TRY(prof_end(h, ev, 1));
+    const int pr_kind = fused ? 0 : (h->cfg.dtype == SAP_F64 ? 2 : 1);
+    SAP_TRY(prof_begin(h, &ev));
+    if (fused) {
+        SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_select<K, TX, true>), dim3(1), dim3(kPairBlock),
+                                             h->tail_lds, h->stream, a, nshort, h->d_P64t,
+                                             h->d_P64r, h->d_Pr, pr_kind, h->cfg.alpha,
+                                             h->cfg.rule, do_step));
+    } else {
+        SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_select<K, TX, false>), dim3(1), dim3(kPairBlock),
+                                             h->tail_lds, h->stream, a, nshort, h->d_P64t,
+                                             h->d_P64r, h->d_Pr, pr_kind, h->cfg.alpha,
+                                             h->cfg.rule, do_step));
+    }
+    SAP_LAUNCHED(h, "k_select");
+    SAP_TRY(prof_end(h, ev, 2));
+    return SAP_OK;
+}
+
 static sap_status enqueue_eval(sap_ctx *h, int do_step, double *tr_min, int64_t *tr_ij,
                                int32_t *tr_cert, int it) {
-    const int K = h->k;
-    const bool f64 = h->cfg.dtype == SAP_F64;
-    uint32_t *gmin = &h->d_st->gmin;
-    hipEvent_t ev = nullptr;
-    if (h->cfg.form == SAP_FUSED) {
-        SAP_TRY(prof_begin(h, &ev));
-        hipLaunchKernelGGL(k_gemm_y, dim3((unsigned)(h->Npad / 64)), dim3(256), 0, h->stream, h->X,
-                           h->cfg.dtype, h->ldx, h->N, h->n, h->k, h->d_mu, h->d_P64t, h->d_Y,
-                           h->kp, h->Npad);
-        SAP_LAUNCHED(h, "k_gemm_y");
-        SAP_TRY(prof_end(h, ev, 0));
-        SAP_TRY(prof_begin(h, &ev));
-        SAP_DISPATCH_K(K, hipLaunchKernelGGL(k_pair_fused<K>, dim3(h->pass_grid), dim3(kPairBlock),
-                                             0, h->stream, h->d_Y, h->kp, h->d_invd2, h->d_tiles,
-                                             h->ntiles, h->d_tmin, gmin));
-        SAP_LAUNCHED(h, "k_pair_fused");
-        SAP_TRY(prof_end(h, ev, 1));
-        SAP_TRY(prof_begin(h, &ev));
-        if (f64) {
-            SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_rescore_fused<K, double>), dim3(h->rescore_grid),
-                                                 dim3(kPairBlock), 0, h->stream, h->d_Y, h->kp,
-                                                 h->d_invd2, h->d_tiles, h->ntiles, h->d_tmin, gmin,
-                                                 h->e_abs, h->e_rel, static_cast<const double *>(h->X),
-                                                 h->ldx, h->n, h->d_P64t, h->d_close, h->nclose,
-                                                 h->d_part));
-        } else {
-            SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_rescore_fused<K, float>), dim3(h->rescore_grid),
-                                                 dim3(kPairBlock), 0, h->stream, h->d_Y, h->kp,
-                                                 h->d_invd2, h->d_tiles, h->ntiles, h->d_tmin, gmin,
-                                                 h->e_abs, h->e_rel, static_cast<const float *>(h->X),
-                                                 h->ldx, h->n, h->d_P64t, h->d_close, h->nclose,
-                                                 h->d_part));
-        }
-        SAP_LAUNCHED(h, "k_rescore_fused");
-        SAP_TRY(prof_end(h, ev, 2));
-    } else {
-        SAP_TRY(prof_begin(h, &ev));
-        if (f64) {
-            const double *S = static_cast<const double *>(h->d_S);
-            const double *Pr = static_cast<const double *>(h->d_Pr);
-            SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_pair_plain<K, double>), dim3(h->pass_grid),
-                                                 dim3(kPairBlock), 0, h->stream, S, h->pcols, h->n,
-                                                 Pr, h->nchunks, h->d_tmin, gmin));
-            SAP_LAUNCHED(h, "k_pair_plain");
-            SAP_TRY(prof_end(h, ev, 1));
-            SAP_TRY(prof_begin(h, &ev));
-            SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_rescore_plain<K, double>), dim3(h->rescore_grid),
-                                                 dim3(kPairBlock), 0, h->stream, S, h->pcols, h->n,
-                                                 Pr, h->nchunks, h->d_tmin, gmin, h->e_abs, h->e_rel,
-                                                 static_cast<const double *>(h->X), h->ldx, h->N,
-                                                 h->d_P64t, h->d_part));
-        } else {
-            const float *S = static_cast<const float *>(h->d_S);
-            const float *Pr = static_cast<const float *>(h->d_Pr);
-            SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_pair_plain<K, float>), dim3(h->pass_grid),
-                                                 dim3(kPairBlock), 0, h->stream, S, h->pcols, h->n,
-                                                 Pr, h->nchunks, h->d_tmin, gmin));
-            SAP_LAUNCHED(h, "k_pair_plain");
-            SAP_TRY(prof_end(h, ev, 1));
-            SAP_TRY(prof_begin(h, &ev));
-            SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_rescore_plain<K, float>), dim3(h->rescore_grid),
-                                                 dim3(kPairBlock), 0, h->stream, S, h->pcols, h->n,
-                                                 Pr, h->nchunks, h->d_tmin, gmin, h->e_abs, h->e_rel,
-                                                 static_cast<const float *>(h->X), h->ldx, h->N,
-                                                 h->d_P64t, h->d_part));
-        }
-        SAP_LAUNCHED(h, "k_rescore_plain");
-        SAP_TRY(prof_end(h, ev, 2));
-    }
-    SAP_TRY(prof_begin(h, &ev));
-    const int pr_kind = h->cfg.form == SAP_PLAIN ? (f64 ? 2 : 1) : 0;
-    if (f64)
-        hipLaunchKernelGGL(k_tail<double>, dim3(1), dim3(64), h->tail_lds, h->stream, h->d_part,
-                           h->rescore_grid, gmin, h->e_abs, h->e_rel,
-                           static_cast<const double *>(h->X), h->ldx, h->N, h->n, h->k, h->d_P64t,
-                           h->d_Pr, pr_kind, h->cfg.alpha, h->cfg.rule, do_step, h->d_res, tr_min,
-                           tr_ij, tr_cert, it);
-    else
-        hipLaunchKernelGGL(k_tail<float>, dim3(1), dim3(64), h->tail_lds, h->stream, h->d_part,
-                           h->rescore_grid, gmin, h->e_abs, h->e_rel,
-                           static_cast<const float *>(h->X), h->ldx, h->N, h->n, h->k, h->d_P64t,
-                           h->d_Pr, pr_kind, h->cfg.alpha, h->cfg.rule, do_step, h->d_res, tr_min,
-                           tr_ij, tr_cert, it);
-    SAP_LAUNCHED(h, "k_tail");
-    SAP_TRY(prof_end(h, ev, 3));
-    return SAP_OK;
+    if (h->cfg.dtype == SAP_F64) return launch_iteration<double>(h, do_step, tr_min, tr_ij, tr_cert, it);
+    return launch_iteration<float>(h, do_step, tr_min, tr_ij, tr_cert, it);
 }
 
 static sap_status read_result(sap_ctx *h, sap_min_result *out) {
@@ -525,25 +551,30 @@ sap_status sap_init(const sap_config *cfg, const void *X, int64_t ldx, const dou
     if (e != hipSuccess) return bail(fail(h, SAP_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
     sap_status s;
     if ((s = dalloc(h, &h->d_P64t, sizeof(double) * h->n * h->k)) != SAP_OK) return bail(s);
+    if ((s = dalloc(h, &h->d_P64r, sizeof(double) * h->n * h->k)) != SAP_OK) return bail(s);
     if ((s = dalloc(h, &h->d_mu, sizeof(double) * h->n)) != SAP_OK) return bail(s);
     if ((s = dalloc(h, &h->d_st, sizeof(DevState))) != SAP_OK) return bail(s);
     if ((s = dalloc(h, &h->d_res, sizeof(DevResult))) != SAP_OK) return bail(s);
-    h->rescore_grid = 256;
-    if ((s = dalloc(h, &h->d_part, sizeof(Partial) * h->rescore_grid)) != SAP_OK) return bail(s);
     if ((s = init_moments(h)) != SAP_OK) return bail(s);
     if ((s = (cfg->form == SAP_PLAIN ? init_plain(h) : init_fused(h))) != SAP_OK) return bail(s);
     if (h->kept == 0) return bail(fail(h, SAP_ERR_NO_PAIRS, "every pair is a duplicate or shorter than min_len"));
+    if ((s = dalloc(h, &h->d_blk, sizeof(uint32_t) * h->pass_grid)) != SAP_OK) return bail(s);
+    if ((s = dalloc(h, &h->d_part, sizeof(Partial) * std::max(h->short_grid, 1))) != SAP_OK) return bail(s);
     if ((s = load_P(h, P0)) != SAP_OK) return bail(s);
     h->tail_lds = sizeof(double) * ((size_t)h->k * h->n + 2 * (size_t)h->n + 16);
-    const void *tails[2] = {reinterpret_cast<const void *>(&k_tail<float>),
-                            reinterpret_cast<const void *>(&k_tail<double>)};
-    for (const void *f : tails) {
-        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->tail_lds);
-        if (e != hipSuccess) return bail(fail(h, SAP_ERR_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(e)));
-    }
-    hipLaunchKernelGGL(k_arm_gmin, dim3(1), dim3(1), 0, h->stream, &h->d_st->gmin);
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    e = hipSuccess;
+    SAP_DISPATCH_K(h->k, {
+        const void *fns[4] = {reinterpret_cast<const void *>(&k_select<K, float, true>),
+                              reinterpret_cast<const void *>(&k_select<K, float, false>),
+                              reinterpret_cast<const void *>(&k_select<K, double, true>),
+                              reinterpret_cast<const void *>(&k_select<K, double, false>)};
+        for (const void *f : fns)
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)h->tail_lds);
+    });
+    if (e != hipSuccess) return bail(fail(h, SAP_ERR_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(e)));
+    e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return bail(fail(h, SAP_ERR_DEVICE, "init: %s", hipGetErrorString(e)));
     *out = h;
     return SAP_OK;

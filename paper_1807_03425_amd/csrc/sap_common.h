@@ -57,6 +57,8 @@ struct DevState {
     int64_t kept, dropped;  // init pair counts
     uint64_t hist[64];   // init: close-pair ladder counts
     int64_t n_close;     // init: length of the close list
+    uint32_t sweep_counter;  // blocks of the running sweep that have finished
+    uint32_t keep_max;       // init: largest 1/d^2 (float bits) left to the coarse pass
     // soft-min
     double sm_m, sm_s;   // running (reference, scaled sum)
     double sm_L;         // loss of the last forward

@@ -208,11 +208,19 @@ __global__ __launch_bounds__(256) void k_build_invd2(const void *X, int dtype, i
 
 // Pairs with 1/d^2 above thr become close pairs: masked in the tile array
 // and appended (in no particular order; the host sorts the list) to `list`.
+// Also folds the largest 1/d^2 left to the coarse pass into *keep_max (as
+// float bits: positive floats order like their bit patterns); the coarse
+// error bound is stated for the shortest pair the coarse pass still sees.
 __global__ __launch_bounds__(256) void k_mark_close(float4 *invd2, const int2 *tiles,
                                                     int64_t ntiles, float thr, int2 *list,
-                                                    int64_t cap, unsigned long long *count) {
+                                                    int64_t cap, unsigned long long *count,
+                                                    unsigned *keep_max) {
+    __shared__ unsigned s_max;
+    if (threadIdx.x == 0) s_max = 0u;
+    __syncthreads();
     const int c = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
+    unsigned mx = 0u;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int2 b = tiles[t];
         for (int m = 0; m < 4; ++m) {
@@ -229,11 +237,16 @@ __global__ __launch_bounds__(256) void k_mark_close(float4 *invd2, const int2 *t
                         list[at] = make_int2(b.x * kTile + 4 * g + rr, b.y * kTile + c);
                     vv[rr] = kMaskClose;
                     hit = true;
+                } else if (vv[rr] > 0.0f) {
+                    mx = max(mx, __float_as_uint(vv[rr]));
                 }
             }
             if (hit) *ptr = make_float4(vv[0], vv[1], vv[2], vv[3]);
         }
     }
+    atomicMax(&s_max, mx);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_max) atomicMax(keep_max, s_max);
 }
 
 }  // namespace sap

@@ -3,24 +3,86 @@
 // One iteration of the method (paper Sec. 4, Algorithm 1) is
 //   evaluate  r_ij = ||P^T s_ij|| for every kept pair, min + argmin,
 //   update    argmax basis vector, modified Gram-Schmidt, alpha shift.
-// Here it runs as
-//   [fused]  k_gemm_y        Y = (X - mu) P in FP64 on the matrix cores -> FP32
-//            k_pair_fused    coarse r~^2 = ||y_i - y_j||^2 / d_ij^2 per 64x64 tile,
-//                            per-tile minimum + global minimum
-//   [plain]  k_pair_plain    coarse r~^2 = ||P^T s||^2 streaming the stored secants
-//   [both]   k_rescore_*     FP64 evaluation, from X, of every pair whose coarse
-//                            value falls in the proven window (and of the
-//                            fused form's short pairs)
-//            k_tail          FP64 min/argmin, record, and the update of P.
+// Here it runs as three launches (two for the plain form):
+//   k_prep    (fused form) Y = (X - mu) P in FP64 on the matrix cores, rounded
+//             to FP32, and in the same grid the FP64 scores of the short
+//             pairs (too short for the coarse error bound; they need no Y);
+//   k_pass    the coarse FP32 score of every pair, reduced to per-unit and
+//             per-block minima (fused: ||y_i - y_j||^2 / d^2 per 16 x 64
+//             sub-tile; plain: ||P^T s||^2 per 256-pair chunk);
+//   k_select  one block: global coarse minimum, the proven rescoring window,
+//             FP64 rescoring of every in-window pair, the FP64 (min, i, j)
+//             record, then the FP64 update of P by one wavefront.
+// No two blocks ever contend on one address: each writes its own result
+// slot, and the kernel boundary is the grid-wide barrier.  (Device-scope
+// atomics on one address serialize across the eight XCDs of the part at tens
+// of nanoseconds each, which costs more than a launch once there are more than
+// a few hundred blocks.)
 //
 // The library is compiled with -ffp-contract=off: every FMA below is
-// written explicitly, so a coarse value recomputed by the rescoring kernel
-// is bit-identical to the one the pass reduced.
+// written explicitly, so a coarse value recomputed by the epilogue is
+// bit-identical to the one the pass reduced.
 #include "sap_common.h"
 
 namespace sap {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ wavefront sums
+
+// DPP lane permutation of a double (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// v + (v of lane ^ 16) and v + (v of lane ^ 32), from gfx950's
+// v_permlane16_swap / v_permlane32_swap: with both operands equal, the two
+// results of the swap are {v_i, v_(i^16)} (resp. ^32) in some order, so their
+// sum is the pair sum (lane semantics measured with an in-bounds probe).
+__device__ __forceinline__ double pair_sum16(double v) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double pair_sum32(double v) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+// Sum over the 64 lanes, identical bits in every lane: each step adds two
+// partial sums that every participating lane sees in swapped order, and
+// floating-point addition is commutative.  Steps inside a 16-lane row use
+// DPP (quad xor 1, quad xor 2, half-row mirror, row mirror); the two
+// cross-row steps use the permlane swaps.  All VALU, no LDS traffic.
+__device__ __forceinline__ double wave_sum_fast(double v) {
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    v = pair_sum16(v);
+    return pair_sum32(v);
+}
+
+// v[from..NV-1] summed over the wavefront, the reductions interleaved.
+template <int NV>
+__device__ __forceinline__ void wave_sum_many(double (&v)[NV], int from = 0) {
+#pragma unroll
+    for (int a = 0; a < NV; ++a) if (a >= from) v[a] += dpp_f64<0xB1>(v[a]);
+#pragma unroll
+    for (int a = 0; a < NV; ++a) if (a >= from) v[a] += dpp_f64<0x4E>(v[a]);
+#pragma unroll
+    for (int a = 0; a < NV; ++a) if (a >= from) v[a] += dpp_f64<0x141>(v[a]);
+#pragma unroll
+    for (int a = 0; a < NV; ++a) if (a >= from) v[a] += dpp_f64<0x140>(v[a]);
+#pragma unroll
+    for (int a = 0; a < NV; ++a) if (a >= from) v[a] += __shfl_xor(v[a], 16, kWave);
+#pragma unroll
+    for (int a = 0; a < NV; ++a) if (a >= from) v[a] += __shfl_xor(v[a], 32, kWave);
+}
 
 // ------------------------------------------------------------------ GEMM
 
@@ -30,24 +92,46 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 //   B (4 x 16):  lane = col + 16 * kk
 //   D (16 x 16): lane holds rows lane/16 + 4 v, v = 0..3, column lane % 16
 //                (measured on gfx950 with an in-bounds probe of the builtin).
-__global__ __launch_bounds__(256) void k_gemm_y(const void *X, int dtype, int64_t ldx,
-                                                int64_t N, int n, int k,
-                                                const double *__restrict__ mu,
-                                                const double *__restrict__ P64t,
-                                                float *__restrict__ Y, int kp, int64_t Npad) {
+// The operand loads of a 64-column chunk are issued before its 16 MFMAs.
+template <typename TX>
+__device__ void gemm_block(const TX *__restrict__ X, int64_t ldx, int64_t N, int n, int k,
+                           const double *__restrict__ mu, const double *__restrict__ P64t,
+                           float *__restrict__ Y, int kp, int64_t Npad) {
     const int lane = threadIdx.x & 63;
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
     if (row0 >= Npad) return;
     const int m = lane & 15, kk = lane >> 4;
     const int64_t row = row0 + m;
     const bool rin = row < N;
+    // out-of-range rows and columns read a valid element and are zeroed by a
+    // mask afterwards, so that every load of a chunk is unconditional and the
+    // 48 of them are in flight together (X is finite: checked at init)
+    const double rmask = rin ? 1.0 : 0.0, pmask = m < k ? 1.0 : 0.0;
+    const TX *xr = X + (rin ? row : N - 1) * ldx;
+    const double *pc = P64t + (int64_t)(m < k ? m : k - 1) * n;
     double4_t acc = {0.0, 0.0, 0.0, 0.0};
-    for (int l0 = 0; l0 < n; l0 += 4) {
+    int l0 = 0;
+    for (; l0 + 64 <= n; l0 += 64) {
+        TX xa[16];
+        double ma[16], pb[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int l = l0 + 4 * s + kk;
+            xa[s] = xr[l];
+            ma[s] = mu[l];
+            pb[s] = pc[l];
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(((double)xa[s] - ma[s]) * rmask, pb[s] * pmask,
+                                                       acc, 0, 0, 0);
+    }
+    for (; l0 < n; l0 += 4) {
         const int l = l0 + kk;
         double a = 0.0, b = 0.0;
         if (l < n) {
-            if (rin) a = load_x(X, dtype, row * ldx + l) - mu[l];
-            if (m < k) b = P64t[(int64_t)m * n + l];
+            if (rin) a = (double)xr[l] - mu[l];
+            if (m < k) b = pc[l];
         }
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
@@ -60,10 +144,10 @@ __global__ __launch_bounds__(256) void k_gemm_y(const void *X, int dtype, int64_
     }
 }
 
-// ------------------------------------------------------------------ fused pass
+// ------------------------------------------------------------------ coarse scores
 
 // Coarse squared ratio of one pair: ||y_i - y_j||^2 * (1/d^2).  y_i is
-// wavefront-uniform (scalar loads), y_j lives in the lane's registers.
+// wavefront-uniform, y_j lives in the lane's registers.
 template <int K>
 __device__ __forceinline__ float pair_r2(const float *__restrict__ yi, const float (&yj)[K],
                                          float w) {
@@ -76,45 +160,20 @@ __device__ __forceinline__ float pair_r2(const float *__restrict__ yi, const flo
     return acc * w;
 }
 
-// One wavefront per tile (grid-stride).  Lane c owns column j = 64 bj + c and
-// walks the 64 rows in 16 float4 groups.  Per pair: K subtractions, K FMAs,
-// one multiply, one unsigned min.
+// The lane's own row of Y (kp is a multiple of 4: float4 loads).
 template <int K>
-__global__ __launch_bounds__(kPairBlock) void k_pair_fused(
-    const float *__restrict__ Y, int kp, const float4 *__restrict__ invd2,
-    const int2 *__restrict__ tiles, int64_t ntiles, uint32_t *__restrict__ tile_min,
-    uint32_t *__restrict__ gmin) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * (kPairBlock / kWave) +
-                        __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t nw = (int64_t)gridDim.x * (kPairBlock / kWave);
-    uint32_t best = kKeyNone;
-    for (int64_t t = wid; t < ntiles; t += nw) {
-        const int2 b = tiles[t];
-        float yj[K];
-        const float *pj = Y + ((int64_t)b.y * kTile + lane) * kp;
+__device__ __forceinline__ void load_yj(const float *__restrict__ Y, int kp, int64_t row,
+                                        float (&yj)[K]) {
+    const float4 *p = reinterpret_cast<const float4 *>(Y + row * kp);
 #pragma unroll
-        for (int c = 0; c < K; ++c) yj[c] = pj[c];
-        const float *yi0 = Y + (int64_t)b.x * kTile * kp;
-        const float4 *tp = invd2 + t * (kTileElems / 4) + lane;
-        uint32_t m = kKeyNone;
-#pragma unroll 2
-        for (int g = 0; g < 16; ++g) {
-            const float4 w = tp[g * 64];
-            const float *yi = yi0 + (int64_t)(4 * g) * kp;
-            m = min(m, __float_as_uint(pair_r2<K>(yi, yj, w.x)));
-            m = min(m, __float_as_uint(pair_r2<K>(yi + kp, yj, w.y)));
-            m = min(m, __float_as_uint(pair_r2<K>(yi + 2 * kp, yj, w.z)));
-            m = min(m, __float_as_uint(pair_r2<K>(yi + 3 * kp, yj, w.w)));
-        }
-        m = wave_min_u32(m);
-        if (lane == 0) tile_min[t] = m;
-        best = min(best, m);
+    for (int c4 = 0; c4 < (K + 3) / 4; ++c4) {
+        const float4 v = p[c4];
+        if (4 * c4 + 0 < K) yj[4 * c4 + 0] = v.x;
+        if (4 * c4 + 1 < K) yj[4 * c4 + 1] = v.y;
+        if (4 * c4 + 2 < K) yj[4 * c4 + 2] = v.z;
+        if (4 * c4 + 3 < K) yj[4 * c4 + 3] = v.w;
     }
-    if (lane == 0 && best < 0x7f800000u) atomicMin(gmin, best);
 }
-
-// ------------------------------------------------------------------ plain pass
 
 template <typename T> struct Vec4;
 template <> struct Vec4<float> {
@@ -137,8 +196,8 @@ template <> struct Vec4<double> {
     }
 };
 
-// Squared projected norms of the 4 consecutive pairs q0..q0+3:
-// c = P^T s accumulated over the n components, then ||c||^2.
+// Plain form: squared projected norms of the 4 consecutive stored secants
+// q0..q0+3 (c = P^T s over the n components, then ||c||^2).
 template <int K, typename T>
 __device__ __forceinline__ void plain_r2(const T *__restrict__ S, int64_t pcols, int n,
                                          const T *__restrict__ Pr, int64_t q0, T (&r2)[4]) {
@@ -175,73 +234,29 @@ __device__ __forceinline__ uint32_t key_of(T r2) {
     return r2 == r2 ? __float_as_uint((float)r2) : kKeyNone;
 }
 
-template <int K, typename T>
-__global__ __launch_bounds__(kPairBlock) void k_pair_plain(
-    const T *__restrict__ S, int64_t pcols, int n, const T *__restrict__ Pr, int64_t nchunks,
-    uint32_t *__restrict__ chunk_min, uint32_t *__restrict__ gmin) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * (kPairBlock / kWave) +
-                        __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t nw = (int64_t)gridDim.x * (kPairBlock / kWave);
-    uint32_t best = kKeyNone;
-    for (int64_t ch = wid; ch < nchunks; ch += nw) {
-        T r2[4];
-        plain_r2<K, T>(S, pcols, n, Pr, ch * kChunk + lane * 4, r2);
-        uint32_t m = kKeyNone;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) m = min(m, key_of<T>(r2[e]));
-        m = wave_min_u32(m);
-        if (lane == 0) chunk_min[ch] = m;
-        best = min(best, m);
-    }
-    if (lane == 0 && best < 0x7f800000u) atomicMin(gmin, best);
-}
+// ------------------------------------------------------------------ FP64 scores
 
-// ------------------------------------------------------------------ FP64 rescoring
-
-// Exact-as-FP64 r of pair (i, j) from X: ||P^T (x_i - x_j)|| / ||x_i - x_j||.
+// FP64 r of pair (i, j) from X: ||P^T (x_i - x_j)|| / ||x_i - x_j||.
 // Wavefront-cooperative (lanes split the n components); every lane returns
 // the same value.
 template <int K, typename TX>
 __device__ double exact_r_wave(const TX *__restrict__ X, int64_t ldx, int n,
                                const double *__restrict__ P64t, int64_t i, int64_t j) {
     const int lane = threadIdx.x & 63;
-    double d2 = 0.0, c[K];
+    double v[K + 1];
 #pragma unroll
-    for (int q = 0; q < K; ++q) c[q] = 0.0;
+    for (int q = 0; q <= K; ++q) v[q] = 0.0;
     for (int l = lane; l < n; l += kWave) {
         const double dl = (double)X[i * ldx + l] - (double)X[j * ldx + l];
-        d2 = __builtin_fma(dl, dl, d2);
+        v[K] = __builtin_fma(dl, dl, v[K]);
 #pragma unroll
-        for (int q = 0; q < K; ++q) c[q] = __builtin_fma(P64t[(int64_t)q * n + l], dl, c[q]);
+        for (int q = 0; q < K; ++q) v[q] = __builtin_fma(P64t[(int64_t)q * n + l], dl, v[q]);
     }
-    d2 = wave_sum(d2);
+    wave_sum_many<K + 1>(v);
     double r2 = 0.0;
 #pragma unroll
-    for (int q = 0; q < K; ++q) {
-        const double cq = wave_sum(c[q]);
-        r2 = __builtin_fma(cq, cq, r2);
-    }
-    return sqrt(r2) / sqrt(d2);
-}
-
-// Same quantity, one lane per pair (sequential over the components).
-template <int K, typename TX>
-__device__ double exact_r_lane(const TX *__restrict__ X, int64_t ldx, int n,
-                               const double *__restrict__ P64t, int64_t i, int64_t j) {
-    double d2 = 0.0, c[K];
-#pragma unroll
-    for (int q = 0; q < K; ++q) c[q] = 0.0;
-    for (int l = 0; l < n; ++l) {
-        const double dl = (double)X[i * ldx + l] - (double)X[j * ldx + l];
-        d2 = __builtin_fma(dl, dl, d2);
-#pragma unroll
-        for (int q = 0; q < K; ++q) c[q] = __builtin_fma(P64t[(int64_t)q * n + l], dl, c[q]);
-    }
-    double r2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < K; ++q) r2 = __builtin_fma(c[q], c[q], r2);
-    return sqrt(r2) / sqrt(d2);
+    for (int q = 0; q < K; ++q) r2 = __builtin_fma(v[q], v[q], r2);
+    return sqrt(r2) / sqrt(v[K]);
 }
 
 // Squared-ratio threshold of the rescoring window.  With coarse values
@@ -268,9 +283,10 @@ __device__ __forceinline__ int bound_broken(double r, double r2c, double e_abs, 
     return fabs(r - rc) > (e_abs + e_rel * fmax(r, rc)) * 1.0001 ? 1 : 0;
 }
 
-// Reduce (r, i, j) and the counters over the block; thread 0 writes the partial.
-__device__ __forceinline__ void block_finish(double r, int32_t i, int32_t j, int32_t nres,
-                                             int32_t ntl, int32_t nviol, Partial *out) {
+// Block-wide reduction of a per-thread (r, i, j) and counters into *out
+// (written by thread 0).  All 256 threads must call it.
+__device__ void block_reduce_partial(double r, int32_t i, int32_t j, int32_t nres, int32_t ntl,
+                                     int32_t nviol, Partial *out) {
     __shared__ Partial sb[kPairBlock / kWave];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     wave_min_lex(r, i, j);
@@ -294,262 +310,486 @@ __device__ __forceinline__ void block_finish(double r, int32_t i, int32_t j, int
         }
         *out = b;
     }
+    __syncthreads();
 }
 
-// Fused form: (a) the short-pair list, one lane per pair; (b) every tile whose
-// minimum is inside the window, revisited by one wavefront, each in-window
-// pair rescored cooperatively.
+__device__ __forceinline__ uint32_t block_min_u32(uint32_t v) {
+    __shared__ uint32_t sm[kPairBlock / kWave];
+    v = wave_min_u32(v);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t b = sm[0];
+#pragma unroll
+    for (int w = 1; w < kPairBlock / kWave; ++w) b = min(b, sm[w]);
+    __syncthreads();
+    return b;
+}
+
+// Load of a value another block of the same grid wrote (after the acquire
+// in finished_last): a device-scope relaxed atomic load, never a scalar load.
+__device__ __forceinline__ uint32_t ld_u32(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------------ sweep
+
+template <typename TX>
+struct SweepArgs {
+    // fused pass
+    const float *Y;
+    int kp;
+    const float4 *invd2;
+    const int2 *tiles;
+    int64_t nhalf;       // 2 x tiles
+    int64_t nb;          // tile rows (the tiles cover the upper triangle of nb x nb)
+    // plain pass
+    const TX *S;
+    int64_t pcols;
+    const TX *Pr;
+    int64_t nchunks;
+    // both passes
+    int n;
+    int npass;           // pass blocks; blocks >= npass are short-pair blocks
+    uint32_t *unit_min;  // per sub-tile (fused) or chunk (plain)
+    uint32_t *blk_min;   // per pass block
+    // short pairs (fused)
+    const int2 *close;
+    const double *cdiff;  // nclose x n, one contiguous difference vector per pair
+    const double *cd;     // their lengths
+    int64_t nclose;
+    int group;            // lanes per short pair (8, 16, 32 or 64)
+    Partial *spart;       // per short-pair block
+    // selection
+    double e_abs, e_rel;
+    const TX *X;
+    int64_t ldx, N;
+    const double *P64t;
+    uint32_t *gmin_out;
+    DevResult *res;
+    double *tr_min;
+    int64_t *tr_ij;
+    int32_t *tr_cert;
+    int it;
+};
+
+// Fused pass block.  One wavefront per half-tile h = 2 t + half (rows
+// 64 bi + 32 half .. +31 against the 64 columns of tile t = (bi, bj);
+// grid-stride over the pass blocks).  Every load of a half-tile is issued
+// up front: its 8 weight float4 per lane, the lane's y_j, and the 32 y_i
+// rows, copied into the wavefront's own LDS slice (read back as broadcasts;
+// no other wavefront touches the slice, so no barrier is needed).
+// Per pair: K subtractions, K FMAs, one multiply, one unsigned min.
 template <int K, typename TX>
-__global__ __launch_bounds__(kPairBlock) void k_rescore_fused(
-    const float *__restrict__ Y, int kp, const float4 *__restrict__ invd2,
-    const int2 *__restrict__ tiles, int64_t ntiles, const uint32_t *__restrict__ tile_min,
-    const uint32_t *__restrict__ gmin, double e_abs, double e_rel, const TX *__restrict__ X,
-    int64_t ldx, int n, const double *__restrict__ P64t, const int2 *__restrict__ close,
-    int64_t nclose, Partial *__restrict__ partials) {
+__device__ uint32_t fused_pass_block(const SweepArgs<TX> &a) {
+    __shared__ float4 s_y[kPairBlock / kWave][32 * kMaxK / 4];
     const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * (kPairBlock / kWave) +
-                        __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t nw = (int64_t)gridDim.x * (kPairBlock / kWave);
-    double coarse, tr;
-    const uint32_t T2 = window_key(*gmin, e_abs, e_rel, &coarse, &tr);
-    double best = __builtin_huge_val();
-    int32_t bi = 0x7fffffff, bj = 0x7fffffff, nres = 0, ntl = 0;
-
-    for (int64_t e = (int64_t)blockIdx.x * kPairBlock + threadIdx.x; e < nclose;
-         e += (int64_t)gridDim.x * kPairBlock) {
-        const int2 pr = close[e];
-        const double r = exact_r_lane<K, TX>(X, ldx, n, P64t, pr.x, pr.y);
-        ++nres;
-        if (lex_less(r, pr.x, pr.y, best, bi, bj)) { best = r; bi = pr.x; bj = pr.y; }
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t wid = (int64_t)blockIdx.x * (kPairBlock / kWave) + wv;
+    const int64_t nw = (int64_t)a.npass * (kPairBlock / kWave);
+    const int kp = a.kp;
+    float4 *yl = s_y[wv];
+    const int nf4 = 8 * kp;   // float4 count of 32 rows of Y
+    uint32_t best = kKeyNone;
+    for (int64_t h = wid; h < a.nhalf; h += nw) {
+        const int64_t t = h >> 1;
+        const int half = (int)(h & 1);
+        const float4 *tp = a.invd2 + t * (kTileElems / 4) + half * 512 + lane;
+        float4 w[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) w[g] = tp[g * 64];
+        const int2 b = a.tiles[t];
+        const float4 *ysrc =
+            reinterpret_cast<const float4 *>(a.Y + ((int64_t)b.x * kTile + 32 * half) * kp);
+        for (int f = lane; f < nf4; f += kWave) yl[f] = ysrc[f];
+        float yj[K];
+        load_yj<K>(a.Y, kp, (int64_t)b.y * kTile + lane, yj);
+        const float *yi0 = reinterpret_cast<const float *>(yl);
+        uint32_t m0 = kKeyNone, m1 = kKeyNone;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            const float *yi = yi0 + 4 * g * kp;
+            uint32_t m = min(__float_as_uint(pair_r2<K>(yi, yj, w[g].x)),
+                             __float_as_uint(pair_r2<K>(yi + kp, yj, w[g].y)));
+            m = min(m, __float_as_uint(pair_r2<K>(yi + 2 * kp, yj, w[g].z)));
+            m = min(m, __float_as_uint(pair_r2<K>(yi + 3 * kp, yj, w[g].w)));
+            if (g < 4) m0 = min(m0, m); else m1 = min(m1, m);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t x0 = __shfl_xor(m0, o, kWave), x1 = __shfl_xor(m1, o, kWave);
+            m0 = min(m0, x0);
+            m1 = min(m1, x1);
+        }
+        if (lane == 0) {
+            a.unit_min[2 * h] = m0;
+            a.unit_min[2 * h + 1] = m1;
+        }
+        best = min(best, min(m0, m1));
     }
+    return block_min_u32(best);
+}
 
-    int32_t nwin = 0, nviol = 0;
+// Plain pass block: one wavefront per 256-pair chunk (grid-stride).
+template <int K, typename TX>
+__device__ uint32_t plain_pass_block(const SweepArgs<TX> &a) {
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t wid = (int64_t)blockIdx.x * (kPairBlock / kWave) + wv;
+    const int64_t nw = (int64_t)a.npass * (kPairBlock / kWave);
+    uint32_t best = kKeyNone;
+    for (int64_t ch = wid; ch < a.nchunks; ch += nw) {
+        TX r2[4];
+        plain_r2<K, TX>(a.S, a.pcols, a.n, a.Pr, ch * kChunk + lane * 4, r2);
+        uint32_t m = kKeyNone;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) m = min(m, key_of<TX>(r2[e]));
+        m = wave_min_u32(m);
+        if (lane == 0) a.unit_min[ch] = m;
+        best = min(best, m);
+    }
+    return block_min_u32(best);
+}
+
+// Short-pair block: `group` lanes per pair split its n components; FP64.
+template <int K, typename TX>
+__device__ void short_block(const SweepArgs<TX> &a, int sb, int nshort) {
+    const int G = a.group;
+    const int sub = threadIdx.x & (G - 1);
+    const int64_t gpb = kPairBlock / G;
+    const int64_t first = (int64_t)sb * gpb + threadIdx.x / G;
+    const int64_t stride = (int64_t)nshort * gpb;
+    const int n = a.n;
+    double best = __builtin_huge_val();
+    int32_t bi = 0x7fffffff, bj = 0x7fffffff, cnt = 0;
+    for (int64_t e = first; e < a.nclose; e += stride) {
+        const double *dv = a.cdiff + e * n;
+        double c[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) c[q] = 0.0;
+        for (int l = sub; l < n; l += G) {
+            const double dl = dv[l];
+#pragma unroll
+            for (int q = 0; q < K; ++q) c[q] = __builtin_fma(a.P64t[(int64_t)q * n + l], dl, c[q]);
+        }
+        for (int o = 1; o < G; o <<= 1)
+#pragma unroll
+            for (int q = 0; q < K; ++q) c[q] += __shfl_xor(c[q], o, kWave);
+        double r2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) r2 = __builtin_fma(c[q], c[q], r2);
+        if (sub == 0) {
+            const double r = sqrt(r2) / a.cd[e];
+            const int2 pr = a.close[e];
+            ++cnt;
+            if (lex_less(r, pr.x, pr.y, best, bi, bj)) { best = r; bi = pr.x; bj = pr.y; }
+        }
+    }
+    block_reduce_partial(best, bi, bj, cnt, 0, 0, a.spart + sb);
+}
+
+
+// Revisit one 16 x 64 sub-tile u (wavefront): every pair whose coarse value is
+// inside the window is rescored in FP64 and its bound re-checked.
+// Tile t of the upper triangle of nb x nb tiles, numbered row by row:
+// t = bi nb - bi (bi - 1) / 2 + (bj - bi).
+__device__ __forceinline__ int2 tile_coords(int64_t t, int64_t nb) {
+    const double c = 2.0 * (double)nb + 1.0;
+    const double disc = c * c - 8.0 * (double)t;
+    int64_t bi = (int64_t)floor((c - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
+    if (bi < 0) bi = 0;
+    if (bi > nb - 1) bi = nb - 1;
+    while (bi > 0 && bi * nb - bi * (bi - 1) / 2 > t) --bi;
+    while (bi < nb - 1 && (bi + 1) * nb - (bi + 1) * bi / 2 <= t) ++bi;
+    const int64_t bj = t - (bi * nb - bi * (bi - 1) / 2) + bi;
+    return make_int2((int)bi, (int)bj);
+}
+
+template <int K, typename TX>
+__device__ void revisit_subtile(const SweepArgs<TX> &a, int64_t u, uint32_t T2, double &best,
+                                int32_t &bi, int32_t &bj, int32_t &nwin, int32_t &nviol) {
+    __shared__ float4 s_ry[kPairBlock / kWave][16 * kMaxK / 4];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int2 b = tile_coords(u >> 2, a.nb);
+    const int32_t row0 = b.x * kTile + (int32_t)(u & 3) * 16;
+    // every load of the sub-tile in flight together; its 16 y_i rows go to
+    // this wavefront's LDS slice (read back as broadcasts)
+    const float4 *tp = a.invd2 + (u >> 2) * (kTileElems / 4) + (u & 3) * 256 + lane;
+    float yj[K];
+    load_yj<K>(a.Y, a.kp, (int64_t)b.y * kTile + lane, yj);
+    const float4 *ysrc = reinterpret_cast<const float4 *>(a.Y + (int64_t)row0 * a.kp);
+    if (lane < 4 * a.kp) s_ry[wv][lane] = ysrc[lane];
+    const float *yi0 = reinterpret_cast<const float *>(s_ry[wv]);
+    // loops kept rolled: one copy of the FP64 evaluation below
+#pragma unroll 1
+    for (int g = 0; g < 4; ++g) {
+        const float4 w4 = tp[g * 64];
+#pragma unroll 1
+        for (int rr = 0; rr < 4; ++rr) {
+            const float wr = rr == 0 ? w4.x : rr == 1 ? w4.y : rr == 2 ? w4.z : w4.w;
+            const float r2 = pair_r2<K>(yi0 + (int64_t)(4 * g + rr) * a.kp, yj, wr);
+            uint64_t cm = __ballot(__float_as_uint(r2) <= T2);
+            while (cm) {
+                const int ln = __builtin_ctzll(cm);
+                cm &= cm - 1;
+                const int32_t i = row0 + 4 * g + rr;
+                const int32_t j = b.y * kTile + ln;
+                const double r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, a.P64t, i, j);
+                const float r2c = __shfl(r2, ln, kWave);
+                ++nwin;
+                nviol += bound_broken(r, (double)r2c, a.e_abs, a.e_rel);
+                if (lex_less(r, i, j, best, bi, bj)) { best = r; bi = i; bj = j; }
+            }
+        }
+    }
+}
+
+// Revisit one 256-pair chunk of the plain form (wavefront).
+template <int K, typename TX>
+__device__ void revisit_chunk(const SweepArgs<TX> &a, int64_t ch, uint32_t T2, double &best,
+                              int32_t &bi, int32_t &bj, int32_t &nwin, int32_t &nviol);
+
+// Selection (one block, after the pass): coarse minimum, window, FP64
+// rescoring, record.  Wavefront w of the block revisits the units that
+// wavefront slot w of each pass block produced, restricted to the pass
+// blocks whose minimum lies inside the window.  Returns the winning pair in
+// every thread (i < 0 if there is none).
+constexpr int kFlagCap = 512;   // flagged pass blocks listed in LDS (else a full scan)
+
+template <int K, typename TX, bool FUSED>
+__device__ int2 select_min(const SweepArgs<TX> &a, int nshort) {
+    __shared__ int s_flag[kFlagCap];
+    __shared__ int s_nflag;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // Code here runs once per launch on a cold instruction cache, so it is
+    // kept to compact loops rather than unrolled straight-line code.
+    // the short-pair partials (already FP64)
+    double best = __builtin_huge_val();
+    int32_t bi = 0x7fffffff, bj = 0x7fffffff, nres_short = 0;
+#pragma unroll 1
+    for (int sb = threadIdx.x; sb < nshort; sb += kPairBlock) {
+        const Partial p = a.spart[sb];
+        if (lex_less(p.r, p.i, p.j, best, bi, bj)) { best = p.r; bi = p.i; bj = p.j; }
+        nres_short += p.n_rescored;
+    }
+    // global coarse minimum over the pass blocks
+    uint32_t g = kKeyNone;
+#pragma unroll 1
+    for (int b = threadIdx.x; b < a.npass; b += 2 * kPairBlock) {
+        const uint32_t v0 = ld_u32(a.blk_min + b);
+        const uint32_t v1 = b + kPairBlock < a.npass ? ld_u32(a.blk_min + b + kPairBlock) : kKeyNone;
+        g = min(g, min(v0, v1));
+    }
+    if (threadIdx.x == 0) s_nflag = 0;
+    g = block_min_u32(g);
+    double coarse, tr;
+    const uint32_t T2 = window_key(g, a.e_abs, a.e_rel, &coarse, &tr);
+    // pass blocks whose minimum lies inside the window
     if (coarse >= 0.0) {
-        for (int64_t t0 = wid * 64; t0 < ntiles; t0 += nw * 64) {
-            const int64_t tl = t0 + lane;
-            const uint32_t tm = tl < ntiles ? tile_min[tl] : kKeyNone;
-            uint64_t hits = __ballot(tm <= T2);
-            while (hits) {
-                const int bit = __builtin_ctzll(hits);
-                hits &= hits - 1;
-                const int64_t t = t0 + bit;
-                ++ntl;
-                const int2 b = tiles[t];
-                float yj[K];
-                const float *pj = Y + ((int64_t)b.y * kTile + lane) * kp;
-#pragma unroll
-                for (int c = 0; c < K; ++c) yj[c] = pj[c];
-                const float *yi0 = Y + (int64_t)b.x * kTile * kp;
-                const float4 *tp = invd2 + t * (kTileElems / 4) + lane;
-                for (int g = 0; g < 16; ++g) {
-                    const float4 w4 = tp[g * 64];
-                    const float wv[4] = {w4.x, w4.y, w4.z, w4.w};
-#pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) {
-                        const float r2 = pair_r2<K>(yi0 + (int64_t)(4 * g + rr) * kp, yj, wv[rr]);
-                        uint64_t cm = __ballot(__float_as_uint(r2) <= T2);
-                        while (cm) {
-                            const int ln = __builtin_ctzll(cm);
-                            cm &= cm - 1;
-                            const int32_t i = b.x * kTile + 4 * g + rr;
-                            const int32_t j = b.y * kTile + ln;
-                            const double r = exact_r_wave<K, TX>(X, ldx, n, P64t, i, j);
-                            const float r2c = __shfl(r2, ln, kWave);
-                            ++nwin;
-                            nviol += bound_broken(r, (double)r2c, e_abs, e_rel);
-                            if (lex_less(r, i, j, best, bi, bj)) { best = r; bi = i; bj = j; }
+#pragma unroll 1
+        for (int b = threadIdx.x; b < a.npass; b += kPairBlock)
+            if (ld_u32(a.blk_min + b) <= T2) {
+                const int at = atomicAdd(&s_nflag, 1);
+                if (at < kFlagCap) s_flag[at] = b;
+            }
+    }
+    __syncthreads();
+    const int nflag = s_nflag;
+    int32_t nres = 0, ntl = 0, nviol = 0, nwin = 0;
+    if (coarse >= 0.0) {
+        const int64_t nw = (int64_t)a.npass * (kPairBlock / kWave);
+        const int64_t nunits_w = FUSED ? a.nhalf : a.nchunks;   // work items of the pass
+        // the list order depends on LDS atomics, but the set does not, and
+        // the result is a lexicographic minimum over the set
+        const bool listed = nflag <= kFlagCap;
+        const int nscan = listed ? nflag : a.npass;
+        for (int f = 0; f < nscan; ++f) {
+            const int b = listed ? s_flag[f] : f;
+            if (!listed && ld_u32(a.blk_min + b) > T2) continue;
+            // the work items of wavefront slot wv of block b, 64 at a time
+            for (int64_t h0 = (int64_t)b * (kPairBlock / kWave) + wv; h0 < nunits_w; h0 += kWave * nw) {
+                const int64_t hl = h0 + lane * nw;
+                uint32_t um = kKeyNone;
+                if (hl < nunits_w) {
+                    if constexpr (FUSED) um = min(ld_u32(a.unit_min + 2 * hl), ld_u32(a.unit_min + 2 * hl + 1));
+                    else um = ld_u32(a.unit_min + hl);
+                }
+                uint64_t hits = __ballot(um <= T2);
+                while (hits) {
+                    const int64_t h = h0 + (int64_t)__builtin_ctzll(hits) * nw;
+                    hits &= hits - 1;
+                    if constexpr (FUSED) {
+                        for (int x = 0; x < 2; ++x) {
+                            const int64_t u = 2 * h + x;
+                            if (ld_u32(a.unit_min + u) <= T2) {
+                                ++ntl;
+                                revisit_subtile<K, TX>(a, u, T2, best, bi, bj, nwin, nviol);
+                            }
                         }
+                    } else {
+                        ++ntl;
+                        revisit_chunk<K, TX>(a, h, T2, best, bi, bj, nwin, nviol);
                     }
                 }
             }
         }
     }
     if (lane != 0) { nwin = 0; ntl = 0; nviol = 0; }
-    block_finish(best, bi, bj, nres + nwin, ntl, nviol, partials + blockIdx.x);
+    nres = nwin + nres_short;
+    __shared__ Partial s_fin;
+    block_reduce_partial(best, bi, bj, nres, ntl, nviol, &s_fin);
+    if (threadIdx.x == 0) {
+        const Partial f = s_fin;
+        const bool found = f.r < __builtin_huge_val();
+        const int cert = (found && f.n_viol == 0) ? 1 : 0;
+        DevResult *res = a.res;
+        res->min_norm = f.r;
+        res->i = found ? f.i : -1;
+        res->j = found ? f.j : -1;
+        res->q = found ? pair_index(a.N, f.i, f.j) : -1;
+        res->coarse_min = coarse;
+        res->window = coarse >= 0.0 ? tr - coarse : 0.0;
+        res->certified = cert;
+        res->n_rescored = f.n_rescored;
+        res->n_tiles = f.n_tiles;
+        res->t = -1;
+        if (a.tr_min) a.tr_min[a.it] = f.r;
+        if (a.tr_ij) {
+            a.tr_ij[2 * a.it] = found ? f.i : -1;
+            a.tr_ij[2 * a.it + 1] = found ? f.j : -1;
+        }
+        if (a.tr_cert) a.tr_cert[a.it] = cert;
+        *a.gmin_out = g;
+    }
+    __syncthreads();
+    const Partial f = s_fin;
+    return f.r < __builtin_huge_val() ? make_int2(f.i, f.j) : make_int2(-1, -1);
 }
 
-__device__ __forceinline__ void decode_q(int64_t q, int64_t N, int64_t &i, int64_t &j) {
-    const double b = 2.0 * (double)N - 1.0;
-    const double disc = b * b - 8.0 * (double)q;
-    int64_t ii = (int64_t)floor((b - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
-    if (ii < 0) ii = 0;
-    if (ii > N - 2) ii = N - 2;
-    while (ii > 0 && pair_index(N, ii, ii + 1) > q) --ii;
-    while (ii < N - 2 && pair_index(N, ii + 1, ii + 2) <= q) ++ii;
-    i = ii;
-    j = q - pair_index(N, ii, ii + 1) + ii + 1;
-}
-
-// Plain form: every chunk whose minimum is inside the window is recomputed
-// by one wavefront and its in-window pairs rescored cooperatively.
-template <int K, typename T>
-__global__ __launch_bounds__(kPairBlock) void k_rescore_plain(
-    const T *__restrict__ S, int64_t pcols, int n, const T *__restrict__ Pr, int64_t nchunks,
-    const uint32_t *__restrict__ chunk_min, const uint32_t *__restrict__ gmin, double e_abs,
-    double e_rel, const T *__restrict__ X, int64_t ldx, int64_t N,
-    const double *__restrict__ P64t, Partial *__restrict__ partials) {
+template <int K, typename TX>
+__device__ void revisit_chunk(const SweepArgs<TX> &a, int64_t ch, uint32_t T2, double &best,
+                              int32_t &bi, int32_t &bj, int32_t &nwin, int32_t &nviol) {
     const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * (kPairBlock / kWave) +
-                        __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t nw = (int64_t)gridDim.x * (kPairBlock / kWave);
-    double coarse, tr;
-    const uint32_t T2 = window_key(*gmin, e_abs, e_rel, &coarse, &tr);
-    double best = __builtin_huge_val();
-    int32_t bi = 0x7fffffff, bj = 0x7fffffff, nwin = 0, ntl = 0, nviol = 0;
-    if (coarse >= 0.0) {
-        for (int64_t c0 = wid * 64; c0 < nchunks; c0 += nw * 64) {
-            const int64_t cl = c0 + lane;
-            const uint32_t cmin = cl < nchunks ? chunk_min[cl] : kKeyNone;
-            uint64_t hits = __ballot(cmin <= T2);
-            while (hits) {
-                const int bit = __builtin_ctzll(hits);
-                hits &= hits - 1;
-                const int64_t ch = c0 + bit;
-                ++ntl;
-                T r2[4];
-                plain_r2<K, T>(S, pcols, n, Pr, ch * kChunk + lane * 4, r2);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    uint64_t cm = __ballot(key_of<T>(r2[e]) <= T2);
-                    while (cm) {
-                        const int ln = __builtin_ctzll(cm);
-                        cm &= cm - 1;
-                        int64_t i, j;
-                        decode_q(ch * kChunk + ln * 4 + e, N, i, j);
-                        const double r = exact_r_wave<K, T>(X, ldx, n, P64t, i, j);
-                        const T r2c = __shfl(r2[e], ln, kWave);
-                        ++nwin;
-                        nviol += bound_broken(r, (double)r2c, e_abs, e_rel);
-                        if (lex_less(r, (int32_t)i, (int32_t)j, best, bi, bj)) {
-                            best = r; bi = (int32_t)i; bj = (int32_t)j;
-                        }
-                    }
-                }
+    TX r2[4];
+    plain_r2<K, TX>(a.S, a.pcols, a.n, a.Pr, ch * kChunk + lane * 4, r2);
+#pragma unroll 1
+    for (int e = 0; e < 4; ++e) {   // rolled: one copy of the FP64 evaluation
+        const TX re = e == 0 ? r2[0] : e == 1 ? r2[1] : e == 2 ? r2[2] : r2[3];
+        uint64_t cm = __ballot(key_of<TX>(re) <= T2);
+        while (cm) {
+            const int ln = __builtin_ctzll(cm);
+            cm &= cm - 1;
+            int64_t i, j;
+            decode_pair(ch * kChunk + ln * 4 + e, a.N, i, j);
+            const double r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, a.P64t, i, j);
+            const TX r2c = __shfl(re, ln, kWave);
+            ++nwin;
+            nviol += bound_broken(r, (double)r2c, a.e_abs, a.e_rel);
+            if (lex_less(r, (int32_t)i, (int32_t)j, best, bi, bj)) {
+                best = r; bi = (int32_t)i; bj = (int32_t)j;
             }
         }
     }
-    if (lane != 0) { nwin = 0; ntl = 0; nviol = 0; }
-    block_finish(best, bi, bj, nwin, ntl, nviol, partials + blockIdx.x);
 }
 
-// ------------------------------------------------------------------ tail: record + update
+// The pass: blocks below npass score pairs coarsely, the others (fused
+// form) score the short pairs in FP64.  Every block writes its own result
+// slot; the kernel boundary is the grid-wide barrier before selection.
+template <int K, typename TX, bool FUSED>
+__global__ __launch_bounds__(kPairBlock) void k_pass(SweepArgs<TX> a) {
+    uint32_t best;
+    if constexpr (FUSED) best = fused_pass_block<K, TX>(a);
+    else best = plain_pass_block<K, TX>(a);
+    if (threadIdx.x == 0) a.blk_min[blockIdx.x] = best;
+}
 
-// Single wavefront.  Reduces the rescoring partials to the FP64 (min, i, j),
-// records it, resets the coarse minimum for the next pass, and (do_step)
-// applies the paper's update to P in FP64:
+// Fused form, before the pass: Y = (X - mu) P (blocks below gemm_blocks) and,
+// in the same launch because they do not need Y, the FP64 scores of the
+// short pairs (the other blocks).
+template <int K, typename TX>
+__global__ __launch_bounds__(kPairBlock) void k_prep(SweepArgs<TX> a, const double *__restrict__ mu,
+                                                     float *__restrict__ Y, int64_t Npad,
+                                                     int gemm_blocks) {
+    if ((int)blockIdx.x < gemm_blocks)
+        gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, a.P64t, Y, a.kp, Npad);
+    else
+        short_block<K, TX>(a, (int)blockIdx.x - gemm_blocks, (int)gridDim.x - gemm_blocks);
+}
+
+// ------------------------------------------------------------------ the update
+
+// One wavefront: the paper's update of P in FP64, from the recorded pair:
 //   c = P^T s;  t = first argmax |c_t|;
 //   if c = 0:   P' = [s, p_2, .., p_k]
 //   else:       v = P c; modified Gram-Schmidt on (v, p_1..p_k without p_t);
 //               u = unit((1-a) v + a (s - v))   [rule 1: unit vectors of v, s-v]
 //               P' = [u, q_2, .., q_k]
-// Vectors live in LDS: A (k x n), s (n), v (n), c (16).  Lane l owns components
-// l, l+64, ...; every inner product is a wavefront butterfly sum.
-template <typename TX>
-__global__ __launch_bounds__(64) void k_tail(
-    const Partial *__restrict__ partials, int nparts, uint32_t *__restrict__ gmin,
-    double e_abs, double e_rel, const TX *__restrict__ X, int64_t ldx, int64_t N, int n, int k,
-    double *__restrict__ P64t, void *__restrict__ Pr, int pr_kind, double alpha, int rule,
-    int do_step, DevResult *__restrict__ res, double *__restrict__ tr_min,
-    int64_t *__restrict__ tr_ij, int32_t *__restrict__ tr_cert, int it) {
-    extern __shared__ double sm[];
-    const int lane = threadIdx.x;
-
-    double r = __builtin_huge_val();
-    int32_t bi = 0x7fffffff, bj = 0x7fffffff, nres = 0, ntl = 0, nviol = 0;
-    for (int p = lane; p < nparts; p += kWave) {
-        const Partial pp = partials[p];
-        if (lex_less(pp.r, pp.i, pp.j, r, bi, bj)) { r = pp.r; bi = pp.i; bj = pp.j; }
-        nres += pp.n_rescored;
-        ntl += pp.n_tiles;
-        nviol += pp.n_viol;
-    }
-    wave_min_lex(r, bi, bj);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        nres += __shfl_xor(nres, o, kWave);
-        ntl += __shfl_xor(ntl, o, kWave);
-        nviol += __shfl_xor(nviol, o, kWave);
-    }
-    double coarse, tr;
-    const uint32_t g = *gmin;
-    (void)window_key(g, e_abs, e_rel, &coarse, &tr);
-    const bool found = r < __builtin_huge_val();
-    if (lane == 0) {
-        res->min_norm = r;
-        res->i = found ? bi : -1;
-        res->j = found ? bj : -1;
-        res->q = found ? pair_index(N, bi, bj) : -1;
-        res->coarse_min = coarse;
-        res->window = coarse >= 0.0 ? tr - coarse : 0.0;
-        res->certified = (found && nviol == 0) ? 1 : 0;
-        res->n_rescored = nres;
-        res->n_tiles = ntl;
-        res->t = -1;
-        if (tr_min) tr_min[it] = r;
-        if (tr_ij) { tr_ij[2 * it] = found ? bi : -1; tr_ij[2 * it + 1] = found ? bj : -1; }
-        if (tr_cert) tr_cert[it] = (found && nviol == 0) ? 1 : 0;
-        // the coarse minimum has been consumed (g was read above); arm it
-        // for the next pass
-        *gmin = kKeyNone;
-    }
-    if (!do_step || !found) return;
-
-    double *A = sm;                       // k x n: MGS vectors
-    double *s = sm + (size_t)k * n;       // unit secant
+// The vectors live in LDS (A: K x n, then s, v, c); lane l owns components
+// l, l+64, ...; every inner product is a wavefront sum.  Modified
+// Gram-Schmidt runs right-looking: once q_m is final, every later vector
+// loses its component along q_m (per vector, the same sequence of
+// subtractions as the column-by-column form).  The loops are deliberately
+// not unrolled: this code runs once per launch, and straight-line code is
+// bound by instruction fetch.
+template <int K, typename TX>
+__device__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
+                             double *__restrict__ P64t, double *__restrict__ P64r,
+                             void *__restrict__ Pr, int pr_kind, double alpha, int rule,
+                             DevResult *__restrict__ res, int64_t i, int64_t j, double *sm) {
+    const int lane = threadIdx.x & 63;
+    double *A = sm;                       // K x n: P (loaded by the caller), then MGS vectors
+    double *s = sm + (size_t)K * n;       // unit secant, later u
     double *v = s + n;                    // P P^T s
-    double *c = v + n;                    // P^T s (uniform)
-    const int64_t i = bi, j = bj;
+    double *c = v + n;                    // P^T s (16 slots)
     double d2 = 0.0;
     for (int l = lane; l < n; l += kWave) {
         const double dl = (double)X[i * ldx + l] - (double)X[j * ldx + l];
         s[l] = dl;
         d2 = __builtin_fma(dl, dl, d2);
     }
-    const double d = sqrt(wave_sum(d2));
+    const double d = sqrt(wave_sum_fast(d2));
     for (int l = lane; l < n; l += kWave) s[l] = s[l] / d;
-
-    // c = P^T s, t = first argmax |c|
+    // c = P^T s, t = first argmax |c_t| (every lane holds the same sums)
     int t = 0;
     double cmax = -1.0;
-    for (int q = 0; q < k; ++q) {
+#pragma unroll 1
+    for (int q = 0; q < K; ++q) {
         double acc = 0.0;
-        for (int l = lane; l < n; l += kWave) acc = __builtin_fma(P64t[(int64_t)q * n + l], s[l], acc);
-        acc = wave_sum(acc);
+        for (int l = lane; l < n; l += kWave) acc = __builtin_fma(A[(size_t)q * n + l], s[l], acc);
+        acc = wave_sum_fast(acc);
         if (lane == 0) c[q] = acc;
         if (fabs(acc) > cmax) { cmax = fabs(acc); t = q; }
     }
-    __syncthreads();
     if (lane == 0) res->t = t;
 
     if (cmax == 0.0) {
-        for (int l = lane; l < n; l += kWave) P64t[l] = s[l];
+        for (int l = lane; l < n; l += kWave) A[l] = s[l];
     } else {
+        // v = P c; MGS input order (v, p_1..p_{t-1}, p_{t+1}..p_k), in place
         for (int l = lane; l < n; l += kWave) {
             double acc = 0.0;
-            for (int q = 0; q < k; ++q) acc = __builtin_fma(P64t[(int64_t)q * n + l], c[q], acc);
+#pragma unroll 1
+            for (int q = 0; q < K; ++q) acc = __builtin_fma(A[(size_t)q * n + l], c[q], acc);
             v[l] = acc;
+            for (int m = t; m > 0; --m) A[(size_t)m * n + l] = A[(size_t)(m - 1) * n + l];
             A[l] = acc;
-            for (int m = 1; m < k; ++m) {
-                const int q = (m - 1 < t) ? m - 1 : m;
-                A[(size_t)m * n + l] = P64t[(int64_t)q * n + l];
-            }
         }
-        // modified Gram-Schmidt, right-looking: once q_m is final, every later
-        // vector loses its component along q_m (the same sequence of
-        // subtractions, per vector, as the textbook column-by-column form)
         double vnorm = 0.0;
-        for (int m = 0; m < k; ++m) {
+#pragma unroll 1
+        for (int m = 0; m < K; ++m) {
             double *am = A + (size_t)m * n;
-            double acc = 0.0;
-            for (int l = lane; l < n; l += kWave) acc = __builtin_fma(am[l], am[l], acc);
-            const double nrm = sqrt(wave_sum(acc));
+            double nn = 0.0;
+            for (int l = lane; l < n; l += kWave) nn = __builtin_fma(am[l], am[l], nn);
+            const double nrm = sqrt(wave_sum_fast(nn));
             if (m == 0) vnorm = nrm;
             for (int l = lane; l < n; l += kWave) am[l] = am[l] / nrm;
-            for (int jv = m + 1; jv < k; ++jv) {
+#pragma unroll 1
+            for (int jv = m + 1; jv < K; ++jv) {
                 double *aj = A + (size_t)jv * n;
                 double dot = 0.0;
                 for (int l = lane; l < n; l += kWave) dot = __builtin_fma(am[l], aj[l], dot);
-                dot = wave_sum(dot);
+                dot = wave_sum_fast(dot);
                 for (int l = lane; l < n; l += kWave) aj[l] = aj[l] - dot * am[l];
             }
         }
@@ -561,7 +801,7 @@ __global__ __launch_bounds__(64) void k_tail(
                 const double w = s[l] - v[l];
                 acc = __builtin_fma(w, w, acc);
             }
-            wn = sqrt(wave_sum(acc));
+            wn = sqrt(wave_sum_fast(acc));
         }
         double un = 0.0;
         for (int l = lane; l < n; l += kWave) {
@@ -570,36 +810,55 @@ __global__ __launch_bounds__(64) void k_tail(
                 u = (1.0 - alpha) * (v[l] / vnorm) + (wn > 0.0 ? alpha * ((s[l] - v[l]) / wn) : 0.0);
             else
                 u = (1.0 - alpha) * v[l] + alpha * (s[l] - v[l]);
-            s[l] = u;  // s is no longer needed: reuse it for u
+            s[l] = u;
             un = __builtin_fma(u, u, un);
         }
-        un = sqrt(wave_sum(un));
-        for (int l = lane; l < n; l += kWave) {
-            P64t[l] = s[l] / un;
-            for (int m = 1; m < k; ++m) P64t[(int64_t)m * n + l] = A[(size_t)m * n + l];
+        const double unrm = sqrt(wave_sum_fast(un));
+        for (int l = lane; l < n; l += kWave) A[l] = s[l] / unrm;
+    }
+    // write back: master (K x n), row-major FP64 copy, and the plain pass's copy
+    for (int l = lane; l < n; l += kWave) {
+#pragma unroll 1
+        for (int q = 0; q < K; ++q) {
+            const double pv = A[(size_t)q * n + l];
+            P64t[(int64_t)q * n + l] = pv;
+            P64r[(int64_t)l * K + q] = pv;
+            if (pr_kind == 1) static_cast<float *>(Pr)[(int64_t)l * K + q] = (float)pv;
+            else if (pr_kind == 2) static_cast<double *>(Pr)[(int64_t)l * K + q] = pv;
         }
     }
-    // the pass's own copy of P (plain form), row-major n x k
-    if (pr_kind == 1) {
-        float *pf = static_cast<float *>(Pr);
-        for (int l = lane; l < n; l += kWave)
-            for (int q = 0; q < k; ++q) pf[(int64_t)l * k + q] = (float)P64t[(int64_t)q * n + l];
-    } else if (pr_kind == 2) {
-        double *pd = static_cast<double *>(Pr);
-        for (int l = lane; l < n; l += kWave)
-            for (int q = 0; q < k; ++q) pd[(int64_t)l * k + q] = P64t[(int64_t)q * n + l];
-    }
+}
+
+// Selection, record and (do_step) update, in one block.  Dynamic LDS holds
+// the update's vectors: (K + 2) n + 16 doubles.
+template <int K, typename TX, bool FUSED>
+__global__ __launch_bounds__(kPairBlock) void k_select(SweepArgs<TX> a, int nshort,
+                                                       double *__restrict__ P64t,
+                                                       double *__restrict__ P64r,
+                                                       void *__restrict__ Pr, int pr_kind,
+                                                       double alpha, int rule, int do_step) {
+    extern __shared__ double sm_dyn[];
+    // P into LDS now, so that its loads overlap the selection
+    if (do_step)
+        for (int e = threadIdx.x; e < K * a.n; e += kPairBlock) sm_dyn[e] = a.P64t[e];
+    const int2 ij = select_min<K, TX, FUSED>(a, nshort);
+    if (do_step && ij.x >= 0 && threadIdx.x < kWave)
+        apply_update<K, TX>(a.X, a.ldx, a.n, P64t, P64r, Pr, pr_kind, alpha, rule, a.res, ij.x,
+                            ij.y, sm_dyn);
 }
 
 // ------------------------------------------------------------------ small helpers
 
-// Write the plain pass's P copy (n x k row-major, T) from the FP64 master.
+// Write the row-major copies of P (FP64, and the plain pass's T) from the master.
 template <typename T>
-__global__ void k_write_pass_P(const double *__restrict__ P64t, int n, int k, T *__restrict__ Pr) {
+__global__ void k_write_P_copies(const double *__restrict__ P64t, int n, int k,
+                                 double *__restrict__ P64r, T *__restrict__ Pr) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * k) return;
     const int l = e / k, q = e % k;
-    Pr[e] = (T)P64t[(int64_t)q * n + l];
+    const double pv = P64t[(int64_t)q * n + l];
+    P64r[e] = pv;
+    if (Pr) Pr[e] = (T)pv;
 }
 
 // P_out (n x k row-major) <- master (k x n)
@@ -610,6 +869,22 @@ __global__ void k_P_out(const double *__restrict__ P64t, int n, int k, double *_
     out[e] = P64t[(int64_t)q * n + l];
 }
 
-__global__ void k_arm_gmin(uint32_t *gmin) { *gmin = kKeyNone; }
+// Difference vectors and lengths of the short pairs, once: cdiff[e*n + l] =
+// x_i[l] - x_j[l] in FP64 (exact for FP32 inputs), cd[e] = ||x_i - x_j||.
+template <typename TX>
+__global__ void k_short_diffs(const TX *__restrict__ X, int64_t ldx, int n,
+                              const int2 *__restrict__ close, int64_t nclose,
+                              double *__restrict__ cdiff, double *__restrict__ cd) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nclose) return;
+    const int2 pr = close[e];
+    double d2 = 0.0;
+    for (int l = 0; l < n; ++l) {
+        const double dl = (double)X[(int64_t)pr.x * ldx + l] - (double)X[(int64_t)pr.y * ldx + l];
+        cdiff[e * n + l] = dl;
+        d2 = __builtin_fma(dl, dl, d2);
+    }
+    cd[e] = sqrt(d2);
+}
 
 }  // namespace sap
