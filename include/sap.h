@@ -152,33 +152,47 @@ sap_status sap_set_stream(sap_handle h, void *stream);
 /* Sizes and error-bound parameters.  Synchronises. */
 sap_status sap_info(sap_handle h, sap_info_t *out);
 
-/* Soft-min surrogate of the minimum (not in the paper; fused form only):
- *   L = -tau log sum_{kept i<j} exp(-r_ij / tau),
- * evaluated for the FP32 projection P (n x k, need not be orthonormal, r is
- * then ||P^T s||).  The scalar L is written to loss[0] (device FP32).  The
- * handle keeps what the backward needs (Y and L), so sap_softmin_bwd must
- * follow its sap_softmin_fwd with the same P and tau.  tau > 0. */
+/* Soft-min surrogate of the minimum (not in the paper; a differentiable
+ * stand-in for Algorithm 1's min; fused form only):
+ *   L = -tau log sum_{kept i<j} exp(-r_ij / tau),   r_ij = ||P^T s_ij||,
+ * for the FP32 projection P (n x k row-major device buffer; it need not be
+ * orthonormal).  r_ij is the coarse FP32 value of the fused pass (its error
+ * bound is that of sap_info), or FP64 for the short pairs.  L is written to
+ * loss[0] (device FP32).  The handle keeps what the backward needs (its own
+ * FP64 copy of P, Y and L), so sap_softmin_bwd differentiates at the P of the
+ * latest sap_softmin_fwd, and must be called with that forward's tau (else
+ * SAP_ERR_INVALID_ARG); a later forward replaces the saved state.
+ * tau in [1e-6, 1e6].  SAP_PLAIN handles return SAP_ERR_UNSUPPORTED.
+ * Asynchronous. */
 sap_status sap_softmin_fwd(sap_handle h, const float *P, double tau,
                            float *loss);
 
-/* Gradient: dP = grad_loss[0] * dL/dP = g * sum w_ij s_ij (P^T s_ij)^T / r_ij,
- * w_ij = exp(-(r_ij - L)/tau).  dP is n x k FP32 (overwritten).  Pairs with
- * r_ij = 0 contribute nothing. */
+/* Gradient at the P of the latest forward (P must be that same projection;
+ * its contents are not read again):
+ *   dP = g dL/dP = g sum_{kept i<j} w_ij s_ij (P^T s_ij)^T / r_ij,
+ * w_ij = exp(-(r_ij - L)/tau) (sum w = 1), g = grad_loss[0] (device FP32).
+ * Contracted as (X - mean)^T Z with z_i = sum_j a_ij (y_i - y_j),
+ * a_ij = w_ij / (d_ij^2 r_ij): the weights are recomputed from Y and 1/d^2,
+ * never stored.  Pairs with r_ij = 0 contribute nothing.  dP is n x k
+ * row-major FP32, overwritten.  Deterministic.  Asynchronous. */
 sap_status sap_softmin_bwd(sap_handle h, const float *P, double tau,
                            const float *grad_loss, float *dP);
 
 /* Per-kernel timing of the iteration, for roofline reporting.  While enabled,
- * every kernel launched by sap_min_secant / sap_step / sap_run is bracketed
- * by a pair of HIP events on the handle's stream (the work itself is
- * unchanged; the events add a small gap between launches).  sap_profile_read
+ * every kernel launched by sap_min_secant / sap_step / sap_run (and by
+ * sap_softmin_fwd / sap_softmin_bwd) is bracketed by a pair of HIP events
+ * on the handle's stream (the work itself is unchanged; the events add a
+ * small gap between launches).  sap_profile_read
  * synchronises, returns the summed durations and launch counts since the
  * last read, and restarts the accumulation.
- * Slots: 0 = Y GEMM (fused form), 1 = pair pass (with the fused form's FP64
- * short pairs), 2 = selection: window, FP64 rescoring, record and update;
- * 3 is unused. */
+ * Slots: 0 = Y GEMM with the fused form's FP64 short pairs, 1 = pair pass,
+ * 2 = selection: window, FP64 rescoring, record and update; soft-min:
+ * 3 = forward tile pass, 4 = backward tile pass, 5 = the other soft-min
+ * launches (P load, Y GEMM, short pairs, merges, the (X - mean)^T Z
+ * contraction); 6 and 7 are unused. */
 typedef struct {
-    double ms[4];
-    int64_t launches[4];
+    double ms[8];
+    int64_t launches[8];
 } sap_profile_t;
 
 sap_status sap_profile_enable(sap_handle h, int32_t on);

@@ -57,10 +57,10 @@ class sap_info_t(C.Structure):
 
 
 class sap_profile_t(C.Structure):
-    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
 
 
-PROFILE_SLOTS = ("gemm", "pass", "select", "unused")
+PROFILE_SLOTS = ("gemm", "pass", "select", "sm_fwd", "sm_bwd", "sm_other")
 
 _lib: Optional[C.CDLL] = None
 
@@ -240,13 +240,17 @@ class SapContext:
 
     # -- soft-min
     def softmin_fwd(self, P, tau: float):
+        """Soft-min loss at P (1-element float32 tensor).  The handle keeps
+        this forward's P, Y and L for the next softmin_bwd."""
         import torch
         P = P.to(device=self._X.device, dtype=torch.float32).contiguous()
         loss = torch.empty(1, dtype=torch.float32, device=self._X.device)
         _check(lib().sap_softmin_fwd(self.handle, _dptr(P), float(tau), _dptr(loss)), self.handle)
+        self._sm_token = getattr(self, "_sm_token", 0) + 1
         return loss
 
     def softmin_bwd(self, P, tau: float, grad_loss):
+        """grad_loss * dL/dP at the P of the last softmin_fwd (same tau)."""
         import torch
         P = P.to(device=self._X.device, dtype=torch.float32).contiguous()
         g = grad_loss.to(device=self._X.device, dtype=torch.float32).reshape(1).contiguous()
@@ -267,13 +271,19 @@ def _make_softmin_function():
         def forward(fctx, P, sap_ctx: SapContext, tau: float):
             loss = sap_ctx.softmin_fwd(P.detach(), tau)
             fctx.sap_ctx, fctx.tau = sap_ctx, tau
+            fctx.token = sap_ctx._sm_token
             fctx.save_for_backward(P.detach())
             return loss.reshape(())
 
         @staticmethod
         def backward(fctx, g):
             (P,) = fctx.saved_tensors
-            dP = fctx.sap_ctx.softmin_bwd(P, fctx.tau, g)
+            c = fctx.sap_ctx
+            if c._sm_token != fctx.token:
+                # another forward ran since this one: recompute its state
+                c.softmin_fwd(P, fctx.tau)
+                fctx.token = c._sm_token
+            dP = c.softmin_bwd(P, fctx.tau, g)
             return dP.to(P.dtype), None, None
 
     return SoftMinSecant

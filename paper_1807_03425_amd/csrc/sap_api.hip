@@ -14,6 +14,7 @@
 // The kernels are compiled into this translation unit (one code object).
 #include "sap_init.hip"
 #include "sap_iter.hip"
+#include "sap_softmin.hip"
 
 using namespace sap;
 
@@ -37,6 +38,8 @@ struct sap_ctx {
     float *d_Y = nullptr;
     int2 *d_close = nullptr;
     double *d_cdiff = nullptr, *d_cd = nullptr;   // short pairs: x_i - x_j (one row each), ||.||
+    // the short-pair list (sorted by (i, j)) as CSR by i and by j
+    int32_t *d_rp_i = nullptr, *d_rp_j = nullptr, *d_permj = nullptr;
 
     // plain
     void *d_S = nullptr;
@@ -55,13 +58,24 @@ struct sap_ctx {
     uint32_t *d_blk = nullptr;   // per pass block minimum
     size_t tail_lds = 0;
 
+    // soft-min (allocated on first use)
+    double *d_smP64t = nullptr;
+    float *d_smY = nullptr;
+    SmPart *d_smpart = nullptr;
+    float *d_smZr = nullptr, *d_smZc = nullptr;
+    double *d_smZ = nullptr, *d_zpair = nullptr, *d_smG = nullptr;
+    int sm_chunks = 0;
+    int64_t sm_rows = 0;
+    bool sm_ready = false;
+    double sm_tau = 0.0;
+
     double radius = 0, close_d = 0, e_abs = 0, e_rel = 0;
     int64_t kept = 0, dropped = 0;
     int64_t dev_bytes = 0;
     std::vector<void *> allocs;
 
     // per-kernel timing (sap_profile_enable)
-    struct Mark { hipEvent_t a, b; int slot; };
+    struct Mark { hipEvent_t a, b; int slot; };   // slots as in sap_profile_t
     bool prof_on = false;
     std::vector<Mark> marks;
     std::vector<hipEvent_t> ev_pool;
@@ -345,6 +359,23 @@ static sap_status init_fused(sap_ctx *h) {
             return a.x != b.x ? a.x < b.x : a.y < b.y;
         });
         SAP_HIP(h, hipMemcpyAsync(h->d_close, lst.data(), sizeof(int2) * want, hipMemcpyHostToDevice, h->stream));
+        // CSR by i (the list order) and by j (a permutation), for the
+        // per-point sums of the soft-min gradient
+        std::vector<int32_t> rp_i((size_t)h->N + 1, 0), rp_j((size_t)h->N + 1, 0), permj((size_t)want);
+        for (const int2 &e : lst) { ++rp_i[(size_t)e.x + 1]; ++rp_j[(size_t)e.y + 1]; }
+        for (int64_t p = 0; p < h->N; ++p) { rp_i[(size_t)p + 1] += rp_i[(size_t)p]; rp_j[(size_t)p + 1] += rp_j[(size_t)p]; }
+        {
+            std::vector<int32_t> fill(rp_j.begin(), rp_j.end() - 1);
+            for (int64_t e = 0; e < want; ++e) permj[(size_t)fill[(size_t)lst[(size_t)e].y]++] = (int32_t)e;
+        }
+        SAP_TRY(dalloc(h, &h->d_rp_i, sizeof(int32_t) * (size_t)(h->N + 1)));
+        SAP_TRY(dalloc(h, &h->d_rp_j, sizeof(int32_t) * (size_t)(h->N + 1)));
+        SAP_TRY(dalloc(h, &h->d_permj, sizeof(int32_t) * (size_t)want));
+        SAP_HIP(h, hipMemcpyAsync(h->d_rp_i, rp_i.data(), sizeof(int32_t) * (h->N + 1), hipMemcpyHostToDevice, h->stream));
+        SAP_HIP(h, hipMemcpyAsync(h->d_rp_j, rp_j.data(), sizeof(int32_t) * (h->N + 1), hipMemcpyHostToDevice, h->stream));
+        SAP_HIP(h, hipMemcpyAsync(h->d_permj, permj.data(), sizeof(int32_t) * want, hipMemcpyHostToDevice, h->stream));
+        // the host vectors must outlive the asynchronous copies
+        SAP_HIP(h, hipStreamSynchronize(h->stream));
         SAP_TRY(dalloc(h, &h->d_cdiff, sizeof(double) * (size_t)h->n * want));
         SAP_TRY(dalloc(h, &h->d_cd, sizeof(double) * (size_t)want));
         const unsigned gblk = (unsigned)ceil_div(want, 256);
@@ -524,6 +555,123 @@ static void destroy_ctx(sap_ctx *h) {
     delete h;
 }
 
+// ---------------------------------------------------------------- soft-min
+
+static sap_status sm_check(sap_ctx *h, const float *P, double tau) {
+    if (h->cfg.form != SAP_FUSED) return fail(h, SAP_ERR_UNSUPPORTED, "soft-min needs the fused form");
+    if (!P) return fail(h, SAP_ERR_INVALID_ARG, "null P");
+    if (!(tau >= 1e-6 && tau <= 1e6)) return fail(h, SAP_ERR_INVALID_ARG, "tau = %g outside [1e-6, 1e6]", tau);
+    return SAP_OK;
+}
+
+static sap_status sm_alloc(sap_ctx *h) {
+    if (h->d_smY) return SAP_OK;
+    const int K = h->k;
+    const int64_t nhalf = 2 * h->ntiles;
+    h->sm_rows = std::max<int64_t>(64, ceil_div(h->N, 256));
+    h->sm_chunks = (int)ceil_div(h->N, h->sm_rows);
+    SAP_TRY(dalloc(h, &h->d_smP64t, sizeof(double) * h->n * K));
+    SAP_TRY(dalloc(h, &h->d_smY, sizeof(float) * (size_t)h->Npad * h->kp));
+    SAP_TRY(dalloc(h, &h->d_smpart, sizeof(SmPart) * (size_t)(h->pass_grid + h->short_grid)));
+    SAP_TRY(dalloc(h, &h->d_smZr, sizeof(float) * (size_t)nhalf * K * 32));
+    SAP_TRY(dalloc(h, &h->d_smZc, sizeof(float) * (size_t)nhalf * K * 64));
+    SAP_TRY(dalloc(h, &h->d_smZ, sizeof(double) * (size_t)h->N * K));
+    SAP_TRY(dalloc(h, &h->d_zpair, sizeof(double) * (size_t)std::max<int64_t>(h->nclose, 1) * K));
+    SAP_TRY(dalloc(h, &h->d_smG, sizeof(double) * (size_t)h->sm_chunks * h->n * K));
+    return SAP_OK;
+}
+
+static SmArgs sm_args(sap_ctx *h, double tau) {
+    SmArgs a{};
+    a.Y = h->d_smY;
+    a.kp = h->kp;
+    a.invd2 = h->d_invd2;
+    a.tiles = h->d_tiles;
+    a.nhalf = 2 * h->ntiles;
+    a.npass = h->pass_grid;
+    a.n = h->n;
+    a.close = h->d_close;
+    a.cdiff = h->d_cdiff;
+    a.cd = h->d_cd;
+    a.nclose = h->nclose;
+    a.group = h->short_group;
+    a.P64t = h->d_smP64t;
+    a.tau = tau;
+    a.c2 = (float)(1.4426950408889634 / tau);   // log2(e) / tau
+    a.part = h->d_smpart;
+    a.Lp = &h->d_st->sm_L;
+    a.Zr = h->d_smZr;
+    a.Zc = h->d_smZc;
+    a.zpair = h->d_zpair;
+    return a;
+}
+
+template <typename TX>
+static sap_status sm_forward(sap_ctx *h, const float *P, double tau, float *loss) {
+    const int K = h->k;
+    hipEvent_t ev = nullptr;
+    const SmArgs a = sm_args(h, tau);
+    const int gemm_blocks = (int)(h->Npad / 64);
+    const int nshort = h->short_grid;
+    SAP_TRY(prof_begin(h, &ev));
+    hipLaunchKernelGGL(k_sm_loadP, dim3((unsigned)ceil_div((int64_t)h->n * K, 256)), dim3(256), 0,
+                       h->stream, P, h->n, K, h->d_smP64t);
+    SAP_LAUNCHED(h, "k_sm_loadP");
+    SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_sm_prep<K, TX>), dim3((unsigned)(gemm_blocks + nshort)),
+                                         dim3(kPairBlock), 0, h->stream, a,
+                                         static_cast<const TX *>(h->X), h->ldx, h->N, h->d_mu,
+                                         h->d_smY, h->Npad, gemm_blocks, 0));
+    SAP_LAUNCHED(h, "k_sm_prep");
+    SAP_TRY(prof_end(h, ev, 5));
+    SAP_TRY(prof_begin(h, &ev));
+    SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_sm_fwd<K>), dim3((unsigned)h->pass_grid), dim3(kPairBlock),
+                                         0, h->stream, a));
+    SAP_LAUNCHED(h, "k_sm_fwd");
+    SAP_TRY(prof_end(h, ev, 3));
+    SAP_TRY(prof_begin(h, &ev));
+    hipLaunchKernelGGL(k_sm_fin, dim3(1), dim3(kPairBlock), 0, h->stream, h->d_smpart,
+                       h->pass_grid + nshort, tau, loss, h->d_st);
+    SAP_LAUNCHED(h, "k_sm_fin");
+    SAP_TRY(prof_end(h, ev, 5));
+    return SAP_OK;
+}
+
+template <typename TX>
+static sap_status sm_backward(sap_ctx *h, double tau, const float *grad_loss, float *dP) {
+    const int K = h->k;
+    hipEvent_t ev = nullptr;
+    const SmArgs a = sm_args(h, tau);
+    const int nshort = h->short_grid;
+    if (nshort > 0) {
+        SAP_TRY(prof_begin(h, &ev));
+        SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_sm_prep<K, TX>), dim3((unsigned)nshort), dim3(kPairBlock),
+                                             0, h->stream, a, static_cast<const TX *>(h->X), h->ldx,
+                                             h->N, h->d_mu, h->d_smY, h->Npad, 0, 1));
+        SAP_LAUNCHED(h, "k_sm_prep");
+        SAP_TRY(prof_end(h, ev, 5));
+    }
+    SAP_TRY(prof_begin(h, &ev));
+    SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_sm_bwd<K>), dim3((unsigned)h->pass_grid), dim3(kPairBlock),
+                                         0, h->stream, a));
+    SAP_LAUNCHED(h, "k_sm_bwd");
+    SAP_TRY(prof_end(h, ev, 4));
+    SAP_TRY(prof_begin(h, &ev));
+    SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_sm_zred<K>), dim3((unsigned)h->nb), dim3(kPairBlock), 0,
+                                         h->stream, a, h->nb, h->N, h->d_rp_i, h->d_rp_j, h->d_permj,
+                                         h->d_smZ));
+    SAP_LAUNCHED(h, "k_sm_zred");
+    const unsigned slices = (unsigned)ceil_div((int64_t)h->n * K, 256);
+    hipLaunchKernelGGL(k_sm_grad<TX>, dim3((unsigned)h->sm_chunks, slices), dim3(256), 0, h->stream,
+                       static_cast<const TX *>(h->X), h->ldx, h->N, h->n, K, h->d_mu, h->d_smZ,
+                       h->sm_rows, h->d_smG);
+    SAP_LAUNCHED(h, "k_sm_grad");
+    hipLaunchKernelGGL(k_sm_dP, dim3(slices), dim3(256), 0, h->stream, h->d_smG, h->sm_chunks, h->n,
+                       K, grad_loss, dP);
+    SAP_LAUNCHED(h, "k_sm_dP");
+    SAP_TRY(prof_end(h, ev, 5));
+    return SAP_OK;
+}
+
 // ---------------------------------------------------------------- C ABI
 
 extern "C" {
@@ -647,15 +795,26 @@ sap_status sap_info(sap_handle h, sap_info_t *out) {
 
 sap_status sap_softmin_fwd(sap_handle h, const float *P, double tau, float *loss) {
     SAP_TRY(usable(h));
-    (void)P; (void)tau; (void)loss;
-    return fail(h, SAP_ERR_UNSUPPORTED, "soft-min is not available in this build");
+    SAP_TRY(sm_check(h, P, tau));
+    if (!loss) return fail(h, SAP_ERR_INVALID_ARG, "null loss pointer");
+    SAP_TRY(sm_alloc(h));
+    h->sm_ready = false;
+    if (h->cfg.dtype == SAP_F64) SAP_TRY(sm_forward<double>(h, P, tau, loss));
+    else SAP_TRY(sm_forward<float>(h, P, tau, loss));
+    h->sm_ready = true;
+    h->sm_tau = tau;
+    return SAP_OK;
 }
 
 sap_status sap_softmin_bwd(sap_handle h, const float *P, double tau, const float *grad_loss,
                            float *dP) {
     SAP_TRY(usable(h));
-    (void)P; (void)tau; (void)grad_loss; (void)dP;
-    return fail(h, SAP_ERR_UNSUPPORTED, "soft-min is not available in this build");
+    SAP_TRY(sm_check(h, P, tau));
+    if (!grad_loss || !dP) return fail(h, SAP_ERR_INVALID_ARG, "null grad_loss or dP");
+    if (!h->sm_ready || tau != h->sm_tau)
+        return fail(h, SAP_ERR_INVALID_ARG, "sap_softmin_bwd must follow sap_softmin_fwd with the same tau");
+    if (h->cfg.dtype == SAP_F64) return sm_backward<double>(h, tau, grad_loss, dP);
+    return sm_backward<float>(h, tau, grad_loss, dP);
 }
 
 sap_status sap_profile_enable(sap_handle h, int32_t on) {

@@ -1,0 +1,418 @@
+// Soft-min surrogate of the minimum projected unit-secant norm, and its
+// gradient in P (gfx950).  Not part of the paper's method: a differentiable
+// stand-in for its min, for gradient-based optimisation of P.
+//
+//   L      = -tau log sum_{kept i<j} exp(-r_ij / tau),   r_ij = ||P^T s_ij||
+//   dL/dP  = sum w_ij s_ij (P^T s_ij)^T / r_ij,          w_ij = exp(-(r_ij - L)/tau)
+//
+// With Y = (X - mu) P, y_i - y_j = P^T (x_i - x_j), and d_ij = ||x_i - x_j||,
+// s (P^T s)^T / r = (x_i - x_j)(y_i - y_j)^T / (d^2 r), so the gradient is a
+// weighted graph Laplacian contraction:
+//   dL/dP = (X - mu)^T Z,   z_i = sum_{j != i} a_ij (y_i - y_j),
+//   a_ij  = w_ij (1/d_ij^2) / r_ij   (0 when r_ij = 0).
+// The weights a_ij are recomputed tile by tile from Y and the stored 1/d^2
+// (never stored), in the same 64 x 64 tile order as the pair pass.  Pairs on
+// the short-pair list (fused form) are evaluated from their FP64 difference
+// vectors, as in the iteration.
+//
+// Launch sequence
+//   forward:  k_sm_loadP   P (FP32, n x k) -> FP64 k x n
+//             k_sm_prep    Y = (X - mu) P (FP64 MFMA, rounded to FP32) and the
+//                          FP64 (min, sum) partials of the short pairs
+//             k_sm_fwd     per-block (min, scaled sum) over the tiles
+//             k_sm_fin     one block: merge in FP64, L, loss
+//   backward: k_sm_prep    (short-pair blocks only) a_ij (y_i - y_j) per short pair
+//             k_sm_bwd     per half-tile partial z sums: rows and columns
+//             k_sm_zred    z_i per point: tile partials + short pairs, FP64
+//             k_sm_grad    (X - mu)^T Z per row chunk, FP64
+//             k_sm_dP      sum of the chunks times dL/dloss
+#include "sap_common.h"
+
+namespace sap {
+
+// log-sum-exp state: reference m and s = sum exp(-(r - m)/tau); s == 0 means
+// empty (m is then ignored)
+struct SmPart {
+    double m, s;
+};
+
+struct SmArgs {
+    const float *Y;        // soft-min Y, Npad x kp
+    int kp;
+    const float4 *invd2;
+    const int2 *tiles;
+    int64_t nhalf;
+    int npass;             // pass blocks; their partials come first in `part`
+    int n;
+    // short pairs
+    const int2 *close;
+    const double *cdiff;
+    const double *cd;
+    int64_t nclose;
+    int group;
+    // parameters
+    const double *P64t;    // soft-min P, k x n FP64
+    double tau;
+    float c2;              // log2(e) / tau
+    SmPart *part;          // npass + nshort partials (forward)
+    const double *Lp;      // L of the forward (backward)
+    // backward partials
+    float *Zr;             // per half-tile: K x 32 row sums
+    float *Zc;             // per half-tile: K x 64 column sums
+    double *zpair;         // per short pair: a (y_i - y_j), K values
+};
+
+// (m1, s1) <- (m1, s1) merged with (m2, s2), FP64.
+__device__ __forceinline__ void lse_merge(double &m1, double &s1, double m2, double s2, double tau) {
+    if (!(s2 > 0.0)) return;
+    if (!(s1 > 0.0)) { m1 = m2; s1 = s2; return; }
+    const double m = fmin(m1, m2);
+    s1 = s1 * exp((m - m1) / tau) + s2 * exp((m - m2) / tau);
+    m1 = m;
+}
+
+// Block-wide merge of per-thread (m, s) into *out (thread 0).  All threads call.
+__device__ void block_lse(double m, double s, double tau, SmPart *out) {
+    __shared__ SmPart sp[kPairBlock / kWave];
+#pragma unroll 1
+    for (int o = 32; o > 0; o >>= 1) {
+        const double m2 = __shfl_xor(m, o, kWave);
+        const double s2 = __shfl_xor(s, o, kWave);
+        lse_merge(m, s, m2, s2, tau);
+    }
+    if ((threadIdx.x & 63) == 0) sp[threadIdx.x >> 6] = SmPart{m, s};
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mm = sp[0].m, ss = sp[0].s;
+        for (int w = 1; w < kPairBlock / kWave; ++w) lse_merge(mm, ss, sp[w].m, sp[w].s, tau);
+        *out = SmPart{mm, ss};
+    }
+}
+
+// P (n x k row-major FP32) -> k x n FP64.
+__global__ void k_sm_loadP(const float *__restrict__ P, int n, int k, double *__restrict__ P64t) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * k) return;
+    const int l = e / k, q = e % k;
+    P64t[(int64_t)q * n + l] = (double)P[e];
+}
+
+// Short pairs in FP64, `group` lanes per pair.  Forward: (min, sum) partial
+// of the block.  Backward: a (y_i - y_j) per pair into zpair.
+template <int K>
+__device__ void sm_short_block(const SmArgs &a, int sb, int nshort, int bwd) {
+    const int G = a.group;
+    const int sub = threadIdx.x & (G - 1);
+    const int64_t gpb = kPairBlock / G;
+    const int64_t first = (int64_t)sb * gpb + threadIdx.x / G;
+    const int64_t stride = (int64_t)nshort * gpb;
+    const int n = a.n;
+    const double tau = a.tau;
+    const double L = bwd ? *a.Lp : 0.0;
+    double m = 0.0, s = 0.0;
+    for (int64_t e = first; e < a.nclose; e += stride) {
+        const double *dv = a.cdiff + e * n;
+        double c[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) c[q] = 0.0;
+        for (int l = sub; l < n; l += G) {
+            const double dl = dv[l];
+#pragma unroll
+            for (int q = 0; q < K; ++q) c[q] = __builtin_fma(a.P64t[(int64_t)q * n + l], dl, c[q]);
+        }
+        for (int o = 1; o < G; o <<= 1)
+#pragma unroll
+            for (int q = 0; q < K; ++q) c[q] += __shfl_xor(c[q], o, kWave);
+        double r2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) r2 = __builtin_fma(c[q], c[q], r2);
+        const double d = a.cd[e];
+        const double r = sqrt(r2) / d;
+        if (!bwd) {
+            if (sub == 0) lse_merge(m, s, r, 1.0, tau);
+        } else {
+            const double coef = r > 0.0 ? exp(-(r - L) / tau) / (r * d * d) : 0.0;
+#pragma unroll
+            for (int q = 0; q < K; ++q)
+                if ((q & (G - 1)) == sub) a.zpair[e * K + q] = coef * c[q];
+        }
+    }
+    if (!bwd) block_lse(m, s, tau, a.part + a.npass + sb);
+}
+
+// Blocks below gemm_blocks: Y = (X - mu) P; the others: short pairs.
+template <int K, typename TX>
+__global__ __launch_bounds__(kPairBlock) void k_sm_prep(SmArgs a, const TX *__restrict__ X,
+                                                        int64_t ldx, int64_t N,
+                                                        const double *__restrict__ mu,
+                                                        float *__restrict__ Y, int64_t Npad,
+                                                        int gemm_blocks, int bwd) {
+    if ((int)blockIdx.x < gemm_blocks)
+        gemm_block<TX>(X, ldx, N, a.n, K, mu, a.P64t, Y, a.kp, Npad);
+    else
+        sm_short_block<K>(a, (int)blockIdx.x - gemm_blocks, (int)gridDim.x - gemm_blocks, bwd);
+}
+
+__device__ __forceinline__ float comp4(const float4 &v, int r) {
+    return r == 0 ? v.x : r == 1 ? v.y : r == 2 ? v.z : v.w;
+}
+
+// Forward pass: one wavefront per half-tile (as the pair pass).  Per lane,
+// the 32 r of a half-tile are reduced to their min m_c and
+// s_c = sum 2^((m_c - r) c2), then folded into the lane's running (m, s).
+// Masked pairs take r = 2e30, beyond the 1e30 start of every min, so their
+// terms underflow to 0.
+template <int K>
+__global__ __launch_bounds__(kPairBlock) void k_sm_fwd(SmArgs a) {
+    __shared__ float4 s_y[kPairBlock / kWave][32 * kMaxK / 4];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t wid = (int64_t)blockIdx.x * (kPairBlock / kWave) + wv;
+    const int64_t nw = (int64_t)a.npass * (kPairBlock / kWave);
+    const int kp = a.kp;
+    const float c2 = a.c2;
+    float4 *yl = s_y[wv];
+    const int nf4 = 8 * kp;
+    float m = 1e30f;
+    double s = 0.0;
+    for (int64_t h = wid; h < a.nhalf; h += nw) {
+        const int64_t t = h >> 1;
+        const int half = (int)(h & 1);
+        const float4 *tp = a.invd2 + t * (kTileElems / 4) + half * 512 + lane;
+        float4 w[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) w[g] = tp[g * 64];
+        const int2 b = a.tiles[t];
+        const float4 *ysrc =
+            reinterpret_cast<const float4 *>(a.Y + ((int64_t)b.x * kTile + 32 * half) * kp);
+        __builtin_amdgcn_wave_barrier();
+        for (int f = lane; f < nf4; f += kWave) yl[f] = ysrc[f];
+        __builtin_amdgcn_wave_barrier();
+        float yj[K];
+        load_yj<K>(a.Y, kp, (int64_t)b.y * kTile + lane, yj);
+        const float *yi0 = reinterpret_cast<const float *>(yl);
+        float r[32];
+        float mc = 1e30f;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const float wt = comp4(w[g], rr);
+                const float acc = pair_r2<K>(yi0 + (4 * g + rr) * kp, yj, 1.0f);
+                const float rv = wt > 0.0f ? __builtin_amdgcn_sqrtf(acc * wt) : 2e30f;
+                r[4 * g + rr] = rv;
+                mc = fminf(mc, rv);
+            }
+        }
+        float sc = 0.0f;
+        const float mcc = mc * c2;
+#pragma unroll
+        for (int e = 0; e < 32; ++e) sc += __builtin_amdgcn_exp2f(__builtin_fmaf(-r[e], c2, mcc));
+        const float mn = fminf(m, mc);
+        s = s * (double)__builtin_amdgcn_exp2f((mn - m) * c2) +
+            (double)(sc * __builtin_amdgcn_exp2f((mn - mc) * c2));
+        m = mn;
+    }
+    block_lse((double)m, s, a.tau, a.part + blockIdx.x);
+}
+
+// Final merge of the forward (one block): L = m - tau log s.
+__global__ __launch_bounds__(kPairBlock) void k_sm_fin(const SmPart *__restrict__ part, int nparts,
+                                                       double tau, float *__restrict__ loss,
+                                                       DevState *st) {
+    double m = 0.0, s = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += kPairBlock) lse_merge(m, s, part[b].m, part[b].s, tau);
+    __shared__ SmPart out;
+    block_lse(m, s, tau, &out);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double L = out.s > 0.0 ? out.m - tau * log(out.s) : __builtin_huge_val();
+        st->sm_m = out.m;
+        st->sm_s = out.s;
+        st->sm_L = L;
+        loss[0] = (float)L;
+    }
+}
+
+// Backward pass: one wavefront per half-tile (rows i = 64 bi + 32 half + 0..31,
+// columns j = 64 bj + lane).  Phase 1 (lane = column): a_ij and the column
+// sums  z_j -= a_ij (y_i - y_j); a_ij goes to the wavefront's LDS block (row
+// stride 65: conflict-free both ways).  Phase 2 (lane = row i = lane % 32,
+// column half lane / 32): z_i += a_ij (y_i - y_j) over its 32 columns, then the
+// two halves are added.  Partials go to Zr / Zc, component-major per half-tile.
+template <int K>
+__global__ __launch_bounds__(kPairBlock) void k_sm_bwd(SmArgs a) {
+    __shared__ float4 s_y[kPairBlock / kWave][32 * kMaxK / 4];
+    __shared__ float4 s_yc[kPairBlock / kWave][64 * kMaxK / 4];
+    __shared__ float s_a[kPairBlock / kWave][32 * 65];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t wid = (int64_t)blockIdx.x * (kPairBlock / kWave) + wv;
+    const int64_t nw = (int64_t)a.npass * (kPairBlock / kWave);
+    const int kp = a.kp;
+    const float c2 = a.c2;
+    const float Lc = (float)(*a.Lp) * c2;
+    float4 *yl = s_y[wv];
+    float4 *ycl = s_yc[wv];
+    float *al = s_a[wv];
+    const int ri = lane & 31, hh = lane >> 5;
+    for (int64_t h = wid; h < a.nhalf; h += nw) {
+        const int64_t t = h >> 1;
+        const int half = (int)(h & 1);
+        const float4 *tp = a.invd2 + t * (kTileElems / 4) + half * 512 + lane;
+        float4 wn = tp[0];
+        const int2 b = a.tiles[t];
+        const float4 *ysrc =
+            reinterpret_cast<const float4 *>(a.Y + ((int64_t)b.x * kTile + 32 * half) * kp);
+        const float4 *ycsrc = reinterpret_cast<const float4 *>(a.Y + (int64_t)b.y * kTile * kp);
+        __builtin_amdgcn_wave_barrier();
+        for (int f = lane; f < 8 * kp; f += kWave) yl[f] = ysrc[f];
+        for (int f = lane; f < 16 * kp; f += kWave) ycl[f] = ycsrc[f];
+        __builtin_amdgcn_wave_barrier();
+        float yj[K];
+        load_yj<K>(a.Y, kp, (int64_t)b.y * kTile + lane, yj);
+        const float *yi0 = reinterpret_cast<const float *>(yl);
+        float zc[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) zc[q] = 0.0f;
+        // phase 1, four rows (one weight float4) per step; the next step's
+        // weights are loaded ahead
+#pragma unroll 1
+        for (int g = 0; g < 8; ++g) {
+            const float4 w4 = wn;
+            if (g < 7) wn = tp[(g + 1) * 64];
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int i = 4 * g + rr;
+                const float wt = comp4(w4, rr);
+                const float *yi = yi0 + i * kp;
+                float d[K];
+                float acc = 0.0f;
+#pragma unroll
+                for (int q = 0; q < K; ++q) {
+                    d[q] = yi[q] - yj[q];
+                    acc = __builtin_fmaf(d[q], d[q], acc);
+                }
+                const float r2 = acc * wt;
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                const float rv = r2 * rinv;
+                const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(-rv, c2, Lc));
+                const float av = (wt > 0.0f && r2 > 0.0f) ? e * wt * rinv : 0.0f;
+#pragma unroll
+                for (int q = 0; q < K; ++q) zc[q] = __builtin_fmaf(-av, d[q], zc[q]);
+                al[i * 65 + lane] = av;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // phase 2
+        float yo[K], zr[K];
+        const float *yown = yi0 + ri * kp;
+#pragma unroll
+        for (int q = 0; q < K; ++q) { yo[q] = yown[q]; zr[q] = 0.0f; }
+        const float *ycf = reinterpret_cast<const float *>(ycl) + hh * 32 * kp;
+        const float *arow = al + ri * 65 + hh * 32;
+#pragma unroll 2
+        for (int jj = 0; jj < 32; ++jj) {
+            const float av = arow[jj];
+            const float *yc = ycf + jj * kp;
+#pragma unroll
+            for (int q = 0; q < K; ++q) zr[q] = __builtin_fmaf(av, yo[q] - yc[q], zr[q]);
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < K; ++q) zr[q] += __shfl_xor(zr[q], 32, kWave);
+        float *zrow = a.Zr + h * (int64_t)(K * 32);
+        float *zcol = a.Zc + h * (int64_t)(K * 64);
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            zcol[q * 64 + lane] = zc[q];
+            if (lane < 32) zrow[q * 32 + lane] = zr[q];
+        }
+    }
+}
+
+// z_p for the 64 points of point block b (one block per point block):
+// row-side partials of tiles (b, bj >= b), column-side partials of tiles
+// (bi <= b, b), then the short pairs through their CSR segments (pairs with
+// i = p add, pairs with j = p subtract).  The four wavefronts split the terms;
+// their sums are added in a fixed order.
+template <int K>
+__global__ __launch_bounds__(kPairBlock) void k_sm_zred(SmArgs a, int64_t nb, int64_t N,
+                                                        const int32_t *__restrict__ rp_i,
+                                                        const int32_t *__restrict__ rp_j,
+                                                        const int32_t *__restrict__ permj,
+                                                        double *__restrict__ Z) {
+    __shared__ double sz[kPairBlock / kWave][64 * K];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int64_t b = blockIdx.x;
+    double z[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) z[q] = 0.0;
+    const int64_t trow0 = b * nb - b * (b - 1) / 2;   // first tile of row b
+    const int half = lane >> 5, rr = lane & 31;
+    for (int64_t bj = b + wv; bj < nb; bj += 4) {
+        const float *zp = a.Zr + (2 * (trow0 + bj - b) + half) * (int64_t)(K * 32) + rr;
+#pragma unroll
+        for (int q = 0; q < K; ++q) z[q] += (double)zp[q * 32];
+    }
+    for (int64_t bi = wv; bi <= b; bi += 4) {
+        const int64_t t = bi * nb - bi * (bi - 1) / 2 + (b - bi);
+        const float *zp = a.Zc + 2 * t * (int64_t)(K * 64) + lane;
+#pragma unroll
+        for (int q = 0; q < K; ++q) z[q] += (double)zp[q * 64] + (double)zp[K * 64 + q * 64];
+    }
+    const int64_t p = b * kTile + lane;
+    if (a.nclose > 0 && p < N) {
+        for (int32_t e = rp_i[p] + wv; e < rp_i[p + 1]; e += 4) {
+#pragma unroll
+            for (int q = 0; q < K; ++q) z[q] += a.zpair[(int64_t)e * K + q];
+        }
+        for (int32_t e = rp_j[p] + wv; e < rp_j[p + 1]; e += 4) {
+            const int64_t ee = permj[e];
+#pragma unroll
+            for (int q = 0; q < K; ++q) z[q] -= a.zpair[ee * K + q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) sz[wv][lane * K + q] = z[q];
+    __syncthreads();
+    if (wv == 0 && p < N) {
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+            Z[p * K + q] = ((sz[0][lane * K + q] + sz[1][lane * K + q]) + sz[2][lane * K + q]) +
+                           sz[3][lane * K + q];
+    }
+}
+
+// G_c = sum_{p in chunk c} (x_p - mu) z_p^T, one output element (l, q) per
+// thread (element e = q n + l: consecutive threads read consecutive x).
+template <typename TX>
+__global__ __launch_bounds__(256) void k_sm_grad(const TX *__restrict__ X, int64_t ldx, int64_t N,
+                                                 int n, int K, const double *__restrict__ mu,
+                                                 const double *__restrict__ Z, int64_t rows,
+                                                 double *__restrict__ Gpart) {
+    const int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * K) return;
+    const int l = (int)(e % n), q = (int)(e / n);
+    const int64_t p0 = (int64_t)blockIdx.x * rows;
+    const int64_t p1 = p0 + rows < N ? p0 + rows : N;
+    const double ml = mu[l];
+    double acc = 0.0;
+    for (int64_t p = p0; p < p1; ++p)
+        acc = __builtin_fma((double)X[p * ldx + l] - ml, Z[p * K + q], acc);
+    Gpart[(int64_t)blockIdx.x * n * K + e] = acc;
+}
+
+// dP (n x k row-major FP32) = dL/dloss * sum over chunks, in chunk order.
+__global__ void k_sm_dP(const double *__restrict__ Gpart, int nchunks, int n, int K,
+                        const float *__restrict__ grad_loss, float *__restrict__ dP) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * K) return;
+    const int l = e % n, q = e / n;
+    double acc = 0.0;
+    for (int c = 0; c < nchunks; ++c) acc += Gpart[(int64_t)c * n * K + e];
+    dP[(int64_t)l * K + q] = (float)((double)grad_loss[0] * acc);
+}
+
+}  // namespace sap
