@@ -11,6 +11,11 @@ FP64-rescored min/argmin, apply the update.  `value` is the fused form's
 secants/s (kept pairs x timed iterations / wall time of the timed region,
 inputs resident in HBM); the plain form is reported beside it.
 
+A second leg times the soft-min surrogate on the synthetic hyperspectral
+workload (N = 20,000 pixels, n = 200 bands, k = 10, tau = 0.01): forward +
+hand-written backward through the library, then Adam on P and a sign-fixed
+QR retraction in torch, per step.
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -63,6 +68,75 @@ def time_form(torch, ctx, steps, warmup, prof_steps):
                 P_final=P_final, profile=prof)
 
 
+def softmin_leg(torch, np, steps, warmup):
+    """ms per soft-min optimisation step (fwd + bwd + Adam + QR) and the
+    library's per-kernel split, on the hyperspectral workload."""
+    import sap_inputs
+    from paper_1807_03425_amd import SapContext, SoftMinSecant
+    dev = torch.device("cuda:0")
+    w = sap_inputs.make("hyper")
+    tau = 0.01
+    t = time.perf_counter()
+    ctx = SapContext(torch.from_numpy(w.X).to(dev), torch.from_numpy(w.P0), form="fused")
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t
+    info = ctx.info()
+    P = torch.nn.Parameter(torch.from_numpy(w.P0.astype(np.float32)).to(dev))
+    opt = torch.optim.Adam([P], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+
+    def one():
+        opt.zero_grad(set_to_none=False)
+        L = SoftMinSecant.apply(P, ctx, tau)
+        L.backward()
+        opt.step()
+        with torch.no_grad():
+            Q, R = torch.linalg.qr(P.detach().double())
+            sg = torch.where(torch.diagonal(R) < 0, -1.0, 1.0).to(Q.dtype)
+            P.copy_((Q * sg.unsqueeze(0)).float())
+        return L
+
+    losses = []
+    for _ in range(warmup):
+        losses.append(one().detach())
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        losses.append(one().detach())
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = max(e0.elapsed_time(e1), wall * 1e3) / steps
+    ctx.profile(True)
+    nprof = min(steps, 10)
+    for _ in range(nprof):
+        one()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.close()
+    pairs = info["n_pairs"]
+    kern = {k: v["ms"] / max(v["launches"], 1) for k, v in prof.items() if v["launches"]}
+    # issue slots per pair (transcendentals count 4): forward K sub + K FMA +
+    # mul + select + sqrt + min + FMA + exp2 + add; backward phase 1 K sub +
+    # K FMA + mul + rsq + mul + FMA + exp2 + 2 mul + 2 cmp + select + K FMA,
+    # phase 2 K sub + K FMA
+    K = w.k
+    slots_fwd, slots_bwd = 2 * K + 14, 5 * K + 16
+    out = dict(workload=f"synthetic hyperspectral, N={w.N}, n={w.n}, k={K}, tau={tau}, "
+                        f"Adam lr=1e-3 + sign-fixed QR retraction",
+               pairs=pairs, steps=steps, warmup=warmup, ms_per_step=ms, init_s=init_s,
+               loss_first=float(losses[0]), loss_last=float(losses[-1]),
+               kernel_ms_per_launch=kern)
+    for slot, slots in (("sm_fwd", slots_fwd), ("sm_bwd", slots_bwd)):
+        if slot in kern:
+            ach = slots * pairs / (kern[slot] / 1e3)
+            out[f"roofline_{slot}"] = dict(bound="alu", achieved=ach / 1e12, peak=VALU_LANE_OPS / 1e12,
+                                           unit="T lane-instr/s", frac=ach / VALU_LANE_OPS,
+                                           slots_per_pair=slots, traffic=None)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +145,8 @@ def main():
     ap.add_argument("--forms", default="fused,plain")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the FP64 CPU oracle baseline (0 disables it)")
+    ap.add_argument("--softmin-steps", type=int, default=20,
+                    help="timed soft-min optimisation steps on the hyperspectral workload (0 disables)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -146,7 +222,8 @@ def main():
     pk = hs["pass_kernel"]
     roofline = dict(bound="hbm", achieved=pk["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=(pk["gbs"] / HBM_PEAK_GBS) if pk["gbs"] else None, traffic=None,
-                    kernel=f"k_pair_{head}", bytes_per_launch=pk["bytes_per_launch"],
+                    kernel=f"sap::k_pass<{w.k}, float, {'true' if head == 'fused' else 'false'}>",
+                    bytes_per_launch=pk["bytes_per_launch"],
                     avg_launch_us=pk["avg_us"], valu_frac=pk["valu_frac"])
 
     accuracy = {}
@@ -207,11 +284,15 @@ def main():
         pp = sums["plain"]["pass_kernel"]
         line["roofline_plain"] = dict(bound="hbm", achieved=pp["gbs"], peak=HBM_PEAK_GBS,
                                       unit="GB/s", frac=pp["gbs"] / HBM_PEAK_GBS if pp["gbs"] else None,
-                                      traffic=None, kernel="k_pair_plain",
+                                      traffic=None, kernel=f"sap::k_pass<{w.k}, float, false>",
                                       bytes_per_launch=pp["bytes_per_launch"],
                                       avg_launch_us=pp["avg_us"])
         if "fused" in sums:
             line["fused_over_plain"] = sums["fused"]["secants_per_s"] / sums["plain"]["secants_per_s"]
+    if args.softmin_steps > 0:
+        log("soft-min leg: hyperspectral workload")
+        line["softmin"] = softmin_leg(torch, np, args.softmin_steps, 3)
+        log(f"soft-min: {line['softmin']['ms_per_step']:.3f} ms/step")
     print(json.dumps(line), flush=True)
 
 

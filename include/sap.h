@@ -180,13 +180,14 @@ sap_status sap_softmin_bwd(sap_handle h, const float *P, double tau,
 
 /* Per-kernel timing of the iteration, for roofline reporting.  While enabled,
  * every kernel launched by sap_min_secant / sap_step / sap_run (and by
- * sap_softmin_fwd / sap_softmin_bwd) is bracketed by a pair of HIP events
- * on the handle's stream (the work itself is unchanged; the events add a
- * small gap between launches).  sap_profile_read
+ * sap_softmin_fwd / sap_softmin_bwd) is timed by the start and end
+ * timestamps of its own dispatch (hipExtLaunchKernelGGL events on the
+ * handle's stream; the work itself is unchanged).  sap_profile_read
  * synchronises, returns the summed durations and launch counts since the
  * last read, and restarts the accumulation.
- * Slots: 0 = Y GEMM with the fused form's FP64 short pairs, 1 = pair pass,
- * 2 = selection: window, FP64 rescoring, record and update; soft-min:
+ * Slots: 0 = Y GEMM (fused form), 1 = pair pass (with the fused form's FP64
+ * short pairs), 2 = selection: window, FP64 rescoring, record and update;
+ * soft-min:
  * 3 = forward tile pass, 4 = backward tile pass, 5 = the other soft-min
  * launches (P load, Y GEMM, short pairs, merges, the (X - mean)^T Z
  * contraction); 6 and 7 are unused. */

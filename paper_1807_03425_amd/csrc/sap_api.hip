@@ -9,6 +9,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "sap_common.h"
 
 // The kernels are compiled into this translation unit (one code object).
@@ -51,6 +53,7 @@ struct sap_ctx {
     double *d_P64r = nullptr;
     double *d_mu = nullptr;
     uint32_t *d_tmin = nullptr;
+    uint32_t *d_tmin2 = nullptr, *d_targ = nullptr;   // plain: per-chunk second key, argmin
     DevState *d_st = nullptr;
     Partial *d_part = nullptr;
     DevResult *d_res = nullptr;
@@ -246,6 +249,8 @@ static sap_status init_plain(sap_ctx *h) {
     SAP_TRY(dalloc(h, &h->d_S, es * (size_t)h->n * (size_t)h->pcols));
     SAP_TRY(dalloc(h, &h->d_Pr, es * (size_t)h->n * h->k));
     SAP_TRY(dalloc(h, &h->d_tmin, sizeof(uint32_t) * h->nchunks));
+    SAP_TRY(dalloc(h, &h->d_tmin2, sizeof(uint32_t) * h->nchunks));
+    SAP_TRY(dalloc(h, &h->d_targ, sizeof(uint32_t) * h->nchunks));
     const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(h->pcols, 256), 65536);
     auto *kept = reinterpret_cast<unsigned long long *>(&h->d_st->kept);
     auto *drop = reinterpret_cast<unsigned long long *>(&h->d_st->dropped);
@@ -400,9 +405,9 @@ static sap_status init_fused(sap_ctx *h) {
     h->pass_grid = (int)std::min<int64_t>(ceil_div(2 * h->ntiles, 4), 8192);   // 4 half-tiles per block
     h->short_group = 8;
     while (h->short_group < 64 && h->short_group * 8 < h->n) h->short_group *= 2;
-    h->short_grid = h->nclose > 0
-                        ? (int)std::min<int64_t>(ceil_div(h->nclose * h->short_group, kPairBlock), 1024)
-                        : 0;
+    // iteration: 64 short pairs per block (16 per wavefront, on the matrix
+    // cores); the soft-min's short-pair blocks use the same grid size
+    h->short_grid = h->nclose > 0 ? (int)std::min<int64_t>(ceil_div(h->nclose, 64), 1024) : 0;
     return SAP_OK;
 }
 
@@ -414,20 +419,20 @@ static sap_status ev_get(sap_ctx *h, hipEvent_t *e) {
     return SAP_OK;
 }
 
-// Bracket the next launch with events when profiling is on.
-static sap_status prof_begin(sap_ctx *h, hipEvent_t *e) {
-    if (!h->prof_on) return SAP_OK;
-    SAP_TRY(ev_get(h, e));
-    SAP_HIP(h, hipEventRecord(*e, h->stream));
-    return SAP_OK;
-}
-
-static sap_status prof_end(sap_ctx *h, hipEvent_t a, int slot) {
-    if (!h->prof_on) return SAP_OK;
-    hipEvent_t b;
-    SAP_TRY(ev_get(h, &b));
-    SAP_HIP(h, hipEventRecord(b, h->stream));
-    h->marks.push_back(sap_ctx::Mark{a, b, slot});
+// Launch on the handle's stream.  With profiling on, the kernel's own start
+// and end timestamps are taken (hipExtLaunchKernelGGL's event pair: no extra
+// packets between launches) and accumulated in `slot`.
+template <typename F, typename... Args>
+static sap_status launch(sap_ctx *h, int slot, const char *what, F kernel, dim3 grid, dim3 block,
+                         uint32_t shmem, Args... args) {
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (h->prof_on) {
+        SAP_TRY(ev_get(h, &ea));
+        SAP_TRY(ev_get(h, &eb));
+    }
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, h->stream, ea, eb, 0, args...);
+    SAP_LAUNCHED(h, what);
+    if (ea) h->marks.push_back(sap_ctx::Mark{ea, eb, slot});
     return SAP_OK;
 }
 
@@ -448,6 +453,8 @@ static SweepArgs<TX> sweep_args(sap_ctx *h, double *tr_min, int64_t *tr_ij, int3
     a.n = h->n;
     a.npass = h->pass_grid;
     a.unit_min = h->d_tmin;
+    a.unit_min2 = h->d_tmin2;
+    a.unit_arg = h->d_targ;
     a.blk_min = h->d_blk;
     a.close = h->d_close;
     a.cdiff = h->d_cdiff;
@@ -476,44 +483,32 @@ static sap_status launch_iteration(sap_ctx *h, int do_step, double *tr_min, int6
                                    int32_t *tr_cert, int it) {
     const int K = h->k;
     const bool fused = h->cfg.form == SAP_FUSED;
-    hipEvent_t ev = nullptr;
     const SweepArgs<TX> a = sweep_args<TX>(h, tr_min, tr_ij, tr_cert, it);
     const int nshort = fused ? h->short_grid : 0;
+    const dim3 blk(kPairBlock);
     if (fused) {
         const int gemm_blocks = (int)(h->Npad / 64);
-        SAP_TRY(prof_begin(h, &ev));
-        SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_prep<K, TX>), dim3((unsigned)(gemm_blocks + nshort)),
-                                             dim3(kPairBlock), 0, h->stream, a, h->d_mu, h->d_Y,
-                                             h->Npad, gemm_blocks));
-        SAP_LAUNCHED(h, "k_prep");
-        SAP_TRY(prof_end(h, ev, 0));
+        const dim3 g0((unsigned)(gemm_blocks + nshort));
+        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 0, "k_prep", k_prep<K, TX>, g0, blk, 0, a, h->d_mu,
+                                         h->d_Y, h->Npad, gemm_blocks)));
     }
-    const dim3 grid((unsigned)h->pass_grid);
-    SAP_TRY(prof_begin(h, &ev));
+    const dim3 g1((unsigned)h->pass_grid);
     if (fused) {
-        SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_pass<K, TX, true>), grid, dim3(kPairBlock), 0,
-                                             h->stream, a));
+        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 1, "k_pass", k_pass<K, TX, true>, g1, blk, 0, a)));
     } else {
-        SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_pass<K, TX, false>), grid, dim3(kPairBlock), 0,
-                                             h->stream, a));
+        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 1, "k_pass", k_pass<K, TX, false>, g1, blk, 0, a)));
     }
-    SAP_LAUNCHED(h, "k_pass");
-    SAP_TRY(prof_end(h, ev, 1));
     const int pr_kind = fused ? 0 : (h->cfg.dtype == SAP_F64 ? 2 : 1);
-    SAP_TRY(prof_begin(h, &ev));
+    const uint32_t lds = (uint32_t)h->tail_lds;
     if (fused) {
-        SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_select<K, TX, true>), dim3(1), dim3(kPairBlock),
-                                             h->tail_lds, h->stream, a, nshort, h->d_P64t,
-                                             h->d_P64r, h->d_Pr, pr_kind, h->cfg.alpha,
-                                             h->cfg.rule, do_step));
+        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 2, "k_select", k_select<K, TX, true>, dim3(1), blk, lds,
+                                         a, nshort, h->d_P64t, h->d_P64r, h->d_Pr, pr_kind,
+                                         h->cfg.alpha, h->cfg.rule, do_step)));
     } else {
-        SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_select<K, TX, false>), dim3(1), dim3(kPairBlock),
-                                             h->tail_lds, h->stream, a, nshort, h->d_P64t,
-                                             h->d_P64r, h->d_Pr, pr_kind, h->cfg.alpha,
-                                             h->cfg.rule, do_step));
+        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 2, "k_select", k_select<K, TX, false>, dim3(1), blk, lds,
+                                         a, nshort, h->d_P64t, h->d_P64r, h->d_Pr, pr_kind,
+                                         h->cfg.alpha, h->cfg.rule, do_step)));
     }
-    SAP_LAUNCHED(h, "k_select");
-    SAP_TRY(prof_end(h, ev, 2));
     return SAP_OK;
 }
 
@@ -609,66 +604,46 @@ static SmArgs sm_args(sap_ctx *h, double tau) {
 template <typename TX>
 static sap_status sm_forward(sap_ctx *h, const float *P, double tau, float *loss) {
     const int K = h->k;
-    hipEvent_t ev = nullptr;
     const SmArgs a = sm_args(h, tau);
     const int gemm_blocks = (int)(h->Npad / 64);
     const int nshort = h->short_grid;
-    SAP_TRY(prof_begin(h, &ev));
-    hipLaunchKernelGGL(k_sm_loadP, dim3((unsigned)ceil_div((int64_t)h->n * K, 256)), dim3(256), 0,
-                       h->stream, P, h->n, K, h->d_smP64t);
-    SAP_LAUNCHED(h, "k_sm_loadP");
-    SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_sm_prep<K, TX>), dim3((unsigned)(gemm_blocks + nshort)),
-                                         dim3(kPairBlock), 0, h->stream, a,
-                                         static_cast<const TX *>(h->X), h->ldx, h->N, h->d_mu,
-                                         h->d_smY, h->Npad, gemm_blocks, 0));
-    SAP_LAUNCHED(h, "k_sm_prep");
-    SAP_TRY(prof_end(h, ev, 5));
-    SAP_TRY(prof_begin(h, &ev));
-    SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_sm_fwd<K>), dim3((unsigned)h->pass_grid), dim3(kPairBlock),
-                                         0, h->stream, a));
-    SAP_LAUNCHED(h, "k_sm_fwd");
-    SAP_TRY(prof_end(h, ev, 3));
-    SAP_TRY(prof_begin(h, &ev));
-    hipLaunchKernelGGL(k_sm_fin, dim3(1), dim3(kPairBlock), 0, h->stream, h->d_smpart,
-                       h->pass_grid + nshort, tau, loss, h->d_st);
-    SAP_LAUNCHED(h, "k_sm_fin");
-    SAP_TRY(prof_end(h, ev, 5));
+    const dim3 blk(kPairBlock);
+    const TX *X = static_cast<const TX *>(h->X);
+    SAP_TRY(launch(h, 5, "k_sm_loadP", k_sm_loadP, dim3((unsigned)ceil_div((int64_t)h->n * K, 256)),
+                   dim3(256), 0, P, h->n, K, h->d_smP64t));
+    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 5, "k_sm_prep", k_sm_prep<K, TX>,
+                                     dim3((unsigned)(gemm_blocks + nshort)), blk, 0, a, X, h->ldx,
+                                     h->N, (const double *)h->d_mu, h->d_smY, h->Npad, gemm_blocks, 0)));
+    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 3, "k_sm_fwd", k_sm_fwd<K>, dim3((unsigned)h->pass_grid), blk,
+                                     0, a)));
+    SAP_TRY(launch(h, 5, "k_sm_fin", k_sm_fin, dim3(1), blk, 0, (const SmPart *)h->d_smpart,
+                   h->pass_grid + nshort, tau, loss, h->d_st));
     return SAP_OK;
 }
 
 template <typename TX>
 static sap_status sm_backward(sap_ctx *h, double tau, const float *grad_loss, float *dP) {
     const int K = h->k;
-    hipEvent_t ev = nullptr;
     const SmArgs a = sm_args(h, tau);
     const int nshort = h->short_grid;
-    if (nshort > 0) {
-        SAP_TRY(prof_begin(h, &ev));
-        SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_sm_prep<K, TX>), dim3((unsigned)nshort), dim3(kPairBlock),
-                                             0, h->stream, a, static_cast<const TX *>(h->X), h->ldx,
-                                             h->N, h->d_mu, h->d_smY, h->Npad, 0, 1));
-        SAP_LAUNCHED(h, "k_sm_prep");
-        SAP_TRY(prof_end(h, ev, 5));
-    }
-    SAP_TRY(prof_begin(h, &ev));
-    SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_sm_bwd<K>), dim3((unsigned)h->pass_grid), dim3(kPairBlock),
-                                         0, h->stream, a));
-    SAP_LAUNCHED(h, "k_sm_bwd");
-    SAP_TRY(prof_end(h, ev, 4));
-    SAP_TRY(prof_begin(h, &ev));
-    SAP_DISPATCH_K(K, hipLaunchKernelGGL((k_sm_zred<K>), dim3((unsigned)h->nb), dim3(kPairBlock), 0,
-                                         h->stream, a, h->nb, h->N, h->d_rp_i, h->d_rp_j, h->d_permj,
-                                         h->d_smZ));
-    SAP_LAUNCHED(h, "k_sm_zred");
+    const dim3 blk(kPairBlock);
+    const TX *X = static_cast<const TX *>(h->X);
+    if (nshort > 0)
+        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 5, "k_sm_prep", k_sm_prep<K, TX>, dim3((unsigned)nshort),
+                                         blk, 0, a, X, h->ldx, h->N, (const double *)h->d_mu,
+                                         h->d_smY, h->Npad, 0, 1)));
+    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 4, "k_sm_bwd", k_sm_bwd<K>, dim3((unsigned)h->pass_grid), blk,
+                                     0, a)));
+    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 5, "k_sm_zred", k_sm_zred<K>, dim3((unsigned)h->nb), blk, 0, a,
+                                     h->nb, h->N, (const int32_t *)h->d_rp_i,
+                                     (const int32_t *)h->d_rp_j, (const int32_t *)h->d_permj,
+                                     h->d_smZ)));
     const unsigned slices = (unsigned)ceil_div((int64_t)h->n * K, 256);
-    hipLaunchKernelGGL(k_sm_grad<TX>, dim3((unsigned)h->sm_chunks, slices), dim3(256), 0, h->stream,
-                       static_cast<const TX *>(h->X), h->ldx, h->N, h->n, K, h->d_mu, h->d_smZ,
-                       h->sm_rows, h->d_smG);
-    SAP_LAUNCHED(h, "k_sm_grad");
-    hipLaunchKernelGGL(k_sm_dP, dim3(slices), dim3(256), 0, h->stream, h->d_smG, h->sm_chunks, h->n,
-                       K, grad_loss, dP);
-    SAP_LAUNCHED(h, "k_sm_dP");
-    SAP_TRY(prof_end(h, ev, 5));
+    SAP_TRY(launch(h, 5, "k_sm_grad", k_sm_grad<TX>, dim3((unsigned)h->sm_chunks, slices), dim3(256), 0,
+                   X, h->ldx, h->N, h->n, K, (const double *)h->d_mu, (const double *)h->d_smZ,
+                   h->sm_rows, h->d_smG));
+    SAP_TRY(launch(h, 5, "k_sm_dP", k_sm_dP, dim3(slices), dim3(256), 0, (const double *)h->d_smG,
+                   h->sm_chunks, h->n, K, grad_loss, dP));
     return SAP_OK;
 }
 
@@ -706,7 +681,14 @@ sap_status sap_init(const sap_config *cfg, const void *X, int64_t ldx, const dou
     if ((s = init_moments(h)) != SAP_OK) return bail(s);
     if ((s = (cfg->form == SAP_PLAIN ? init_plain(h) : init_fused(h))) != SAP_OK) return bail(s);
     if (h->kept == 0) return bail(fail(h, SAP_ERR_NO_PAIRS, "every pair is a duplicate or shorter than min_len"));
-    if ((s = dalloc(h, &h->d_blk, sizeof(uint32_t) * h->pass_grid)) != SAP_OK) return bail(s);
+    {
+        // padded to whole uint4 x 256-thread loads of the selection, with keys
+        // that lose every minimum
+        const size_t nblk = (size_t)ceil_div(h->pass_grid, 4 * kPairBlock) * 4 * kPairBlock;
+        if ((s = dalloc(h, &h->d_blk, sizeof(uint32_t) * nblk)) != SAP_OK) return bail(s);
+        e = hipMemsetAsync(h->d_blk, 0xFF, sizeof(uint32_t) * nblk, h->stream);
+        if (e != hipSuccess) return bail(fail(h, SAP_ERR_DEVICE, "hipMemsetAsync: %s", hipGetErrorString(e)));
+    }
     if ((s = dalloc(h, &h->d_part, sizeof(Partial) * std::max(h->short_grid, 1))) != SAP_OK) return bail(s);
     if ((s = load_P(h, P0)) != SAP_OK) return bail(s);
     h->tail_lds = sizeof(double) * ((size_t)h->k * h->n + 2 * (size_t)h->n + 16);

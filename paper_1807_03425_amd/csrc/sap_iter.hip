@@ -6,10 +6,12 @@
 // Here it runs as three launches (two for the plain form):
 //   k_prep    (fused form) Y = (X - mu) P in FP64 on the matrix cores, rounded
 //             to FP32, and in the same grid the FP64 scores of the short
-//             pairs (too short for the coarse error bound; they need no Y);
+//             pairs (too short for the coarse error bound), also on the
+//             matrix cores: P^T (x_i - x_j) from stored differences;
 //   k_pass    the coarse FP32 score of every pair, reduced to per-unit and
 //             per-block minima (fused: ||y_i - y_j||^2 / d^2 per 16 x 64
-//             sub-tile; plain: ||P^T s||^2 per 256-pair chunk);
+//             sub-tile; plain: ||P^T s||^2 per 256-pair chunk, with the
+//             chunk's argmin and second-smallest score);
 //   k_select  one block: global coarse minimum, the proven rescoring window,
 //             FP64 rescoring of every in-window pair, the FP64 (min, i, j)
 //             record, then the FP64 update of P by one wavefront.
@@ -236,12 +238,12 @@ __device__ __forceinline__ uint32_t key_of(T r2) {
 
 // ------------------------------------------------------------------ FP64 scores
 
-// FP64 r of pair (i, j) from X: ||P^T (x_i - x_j)|| / ||x_i - x_j||.
-// Wavefront-cooperative (lanes split the n components); every lane returns
-// the same value.
+// FP64 r of pair (i, j) from X: ||P^T (x_i - x_j)|| / ||x_i - x_j||, with
+// P (K x n, FP64) in LDS.  Wavefront-cooperative (lanes split the n
+// components); every lane returns the same value.
 template <int K, typename TX>
 __device__ double exact_r_wave(const TX *__restrict__ X, int64_t ldx, int n,
-                               const double *__restrict__ P64t, int64_t i, int64_t j) {
+                               const double *P64t, int64_t i, int64_t j) {
     const int lane = threadIdx.x & 63;
     double v[K + 1];
 #pragma unroll
@@ -351,6 +353,8 @@ struct SweepArgs {
     int n;
     int npass;           // pass blocks; blocks >= npass are short-pair blocks
     uint32_t *unit_min;  // per sub-tile (fused) or chunk (plain)
+    uint32_t *unit_min2; // plain: second-smallest key of the chunk
+    uint32_t *unit_arg;  // plain: position (0..255) of the chunk's smallest key
     uint32_t *blk_min;   // per pass block
     // short pairs (fused)
     const int2 *close;
@@ -440,53 +444,96 @@ __device__ uint32_t plain_pass_block(const SweepArgs<TX> &a) {
     for (int64_t ch = wid; ch < a.nchunks; ch += nw) {
         TX r2[4];
         plain_r2<K, TX>(a.S, a.pcols, a.n, a.Pr, ch * kChunk + lane * 4, r2);
-        uint32_t m = kKeyNone;
+        uint32_t kk[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) m = min(m, key_of<TX>(r2[e]));
-        m = wave_min_u32(m);
-        if (lane == 0) a.unit_min[ch] = m;
-        best = min(best, m);
+        for (int e = 0; e < 4; ++e) kk[e] = key_of<TX>(r2[e]);
+        // the chunk's smallest and second-smallest keys: the selection
+        // rescores a chunk's single window pair directly, without a rescan,
+        // when the second-smallest key lies outside the window
+        uint32_t m1 = min(kk[0], kk[1]), m2 = max(kk[0], kk[1]);
+#pragma unroll
+        for (int e = 2; e < 4; ++e) { m2 = min(m2, max(m1, kk[e])); m1 = min(m1, kk[e]); }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t x1 = __shfl_xor(m1, o, kWave), x2 = __shfl_xor(m2, o, kWave);
+            m2 = min(min(m2, x2), max(m1, x1));
+            m1 = min(m1, x1);
+        }
+        // position of the first pair holding the smallest key
+        const int ef = kk[0] == m1 ? 0 : kk[1] == m1 ? 1 : kk[2] == m1 ? 2 : kk[3] == m1 ? 3 : 4;
+        const uint64_t bal = __ballot(ef < 4);
+        const int fl = bal ? __builtin_ctzll(bal) : 0;
+        const int arg = fl * 4 + __shfl(ef, fl, kWave);
+        if (lane == 0) {
+            a.unit_min[ch] = m1;
+            a.unit_min2[ch] = m2;
+            a.unit_arg[ch] = (uint32_t)arg;
+        }
+        best = min(best, m1);
     }
     return block_min_u32(best);
 }
 
-// Short-pair block: `group` lanes per pair split its n components; FP64.
+// Short pairs in FP64 on the matrix cores: c = P^T (x_i - x_j) for every
+// pair, from the pairs' difference vectors (one row of n each), tiled exactly as gemm_block
+// (16 pairs per wavefront, grid-stride over groups of 16).  In the output
+// layout the 16 lanes of a DPP row hold the K (<= 16) components of one
+// pair's c, so ||c||^2 is four in-row DPP steps.  r = ||c|| / d, reduced to
+// the block's lexicographic (r, i, j) minimum.
 template <int K, typename TX>
 __device__ void short_block(const SweepArgs<TX> &a, int sb, int nshort) {
-    const int G = a.group;
-    const int sub = threadIdx.x & (G - 1);
-    const int64_t gpb = kPairBlock / G;
-    const int64_t first = (int64_t)sb * gpb + threadIdx.x / G;
-    const int64_t stride = (int64_t)nshort * gpb;
+    const int lane = threadIdx.x & 63;
+    const int m = lane & 15, kk = lane >> 4;
     const int n = a.n;
+    const int64_t ngroups = (a.nclose + 15) / 16;
+    const double pmask = m < K ? 1.0 : 0.0;
+    const double *pc = a.P64t + (int64_t)(m < K ? m : K - 1) * n;
     double best = __builtin_huge_val();
     int32_t bi = 0x7fffffff, bj = 0x7fffffff, cnt = 0;
-    for (int64_t e = first; e < a.nclose; e += stride) {
-        const double *dv = a.cdiff + e * n;
-        double c[K];
+    for (int64_t g16 = (int64_t)sb * (kPairBlock / kWave) + (threadIdx.x >> 6); g16 < ngroups;
+         g16 += (int64_t)nshort * (kPairBlock / kWave)) {
+        const int64_t row = g16 * 16 + m;
+        const bool rin = row < a.nclose;
+        const double rmask = rin ? 1.0 : 0.0;
+        const double *dr = a.cdiff + (rin ? row : a.nclose - 1) * n;
+        double4_t acc = {0.0, 0.0, 0.0, 0.0};
+        int l0 = 0;
+        for (; l0 + 64 <= n; l0 += 64) {
+            double xa[16], pb[16];
 #pragma unroll
-        for (int q = 0; q < K; ++q) c[q] = 0.0;
-        for (int l = sub; l < n; l += G) {
-            const double dl = dv[l];
+            for (int q = 0; q < 16; ++q) {
+                xa[q] = dr[l0 + 4 * q + kk];
+                pb[q] = pc[l0 + 4 * q + kk];
+            }
 #pragma unroll
-            for (int q = 0; q < K; ++q) c[q] = __builtin_fma(a.P64t[(int64_t)q * n + l], dl, c[q]);
+            for (int q = 0; q < 16; ++q)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[q] * rmask, pb[q] * pmask, acc, 0, 0, 0);
         }
-        for (int o = 1; o < G; o <<= 1)
+        for (; l0 < n; l0 += 4) {
+            const int l = l0 + kk;
+            const double x = (l < n && rin) ? dr[l] : 0.0;
+            const double p = (l < n && m < K) ? pc[l] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, p, acc, 0, 0, 0);
+        }
+        // lane holds c[row kk + 4 v][column m]
 #pragma unroll
-            for (int q = 0; q < K; ++q) c[q] += __shfl_xor(c[q], o, kWave);
-        double r2 = 0.0;
-#pragma unroll
-        for (int q = 0; q < K; ++q) r2 = __builtin_fma(c[q], c[q], r2);
-        if (sub == 0) {
-            const double r = sqrt(r2) / a.cd[e];
-            const int2 pr = a.close[e];
-            ++cnt;
-            if (lex_less(r, pr.x, pr.y, best, bi, bj)) { best = r; bi = pr.x; bj = pr.y; }
+        for (int v = 0; v < 4; ++v) {
+            double q2 = acc[v] * acc[v];
+            q2 += dpp_f64<0xB1>(q2);
+            q2 += dpp_f64<0x4E>(q2);
+            q2 += dpp_f64<0x141>(q2);
+            q2 += dpp_f64<0x140>(q2);
+            const int64_t e = g16 * 16 + kk + 4 * v;
+            if (m == 0 && e < a.nclose) {
+                const double r = sqrt(q2) / a.cd[e];
+                const int2 pr = a.close[e];
+                ++cnt;
+                if (lex_less(r, pr.x, pr.y, best, bi, bj)) { best = r; bi = pr.x; bj = pr.y; }
+            }
         }
     }
     block_reduce_partial(best, bi, bj, cnt, 0, 0, a.spart + sb);
 }
-
 
 // Revisit one 16 x 64 sub-tile u (wavefront): every pair whose coarse value is
 // inside the window is rescored in FP64 and its bound re-checked.
@@ -505,25 +552,29 @@ __device__ __forceinline__ int2 tile_coords(int64_t t, int64_t nb) {
 }
 
 template <int K, typename TX>
-__device__ void revisit_subtile(const SweepArgs<TX> &a, int64_t u, uint32_t T2, double &best,
-                                int32_t &bi, int32_t &bj, int32_t &nwin, int32_t &nviol) {
+__device__ void revisit_subtile(const SweepArgs<TX> &a, const double *Pl, int64_t u, uint32_t T2,
+                                double &best, int32_t &bi, int32_t &bj, int32_t &nwin,
+                                int32_t &nviol) {
     __shared__ float4 s_ry[kPairBlock / kWave][16 * kMaxK / 4];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int2 b = tile_coords(u >> 2, a.nb);
     const int32_t row0 = b.x * kTile + (int32_t)(u & 3) * 16;
-    // every load of the sub-tile in flight together; its 16 y_i rows go to
-    // this wavefront's LDS slice (read back as broadcasts)
+    // every load of the sub-tile issued together; its 16 y_i rows go to this
+    // wavefront's LDS slice (read back as broadcasts)
     const float4 *tp = a.invd2 + (u >> 2) * (kTileElems / 4) + (u & 3) * 256 + lane;
+    const float4 w0 = tp[0], w1 = tp[64], w2 = tp[128], w3 = tp[192];
     float yj[K];
     load_yj<K>(a.Y, a.kp, (int64_t)b.y * kTile + lane, yj);
     const float4 *ysrc = reinterpret_cast<const float4 *>(a.Y + (int64_t)row0 * a.kp);
+    __builtin_amdgcn_wave_barrier();
     if (lane < 4 * a.kp) s_ry[wv][lane] = ysrc[lane];
+    __builtin_amdgcn_wave_barrier();
     const float *yi0 = reinterpret_cast<const float *>(s_ry[wv]);
     // loops kept rolled: one copy of the FP64 evaluation below
 #pragma unroll 1
     for (int g = 0; g < 4; ++g) {
-        const float4 w4 = tp[g * 64];
+        const float4 w4 = g == 0 ? w0 : g == 1 ? w1 : g == 2 ? w2 : w3;
 #pragma unroll 1
         for (int rr = 0; rr < 4; ++rr) {
             const float wr = rr == 0 ? w4.x : rr == 1 ? w4.y : rr == 2 ? w4.z : w4.w;
@@ -534,7 +585,7 @@ __device__ void revisit_subtile(const SweepArgs<TX> &a, int64_t u, uint32_t T2, 
                 cm &= cm - 1;
                 const int32_t i = row0 + 4 * g + rr;
                 const int32_t j = b.y * kTile + ln;
-                const double r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, a.P64t, i, j);
+                const double r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, Pl, i, j);
                 const float r2c = __shfl(r2, ln, kWave);
                 ++nwin;
                 nviol += bound_broken(r, (double)r2c, a.e_abs, a.e_rel);
@@ -542,57 +593,96 @@ __device__ void revisit_subtile(const SweepArgs<TX> &a, int64_t u, uint32_t T2, 
             }
         }
     }
+    __builtin_amdgcn_wave_barrier();
 }
 
-// Revisit one 256-pair chunk of the plain form (wavefront).
+// Rescan one 256-pair chunk of the plain form (wavefront): used only when the
+// chunk may hold more than one window pair.
 template <int K, typename TX>
-__device__ void revisit_chunk(const SweepArgs<TX> &a, int64_t ch, uint32_t T2, double &best,
-                              int32_t &bi, int32_t &bj, int32_t &nwin, int32_t &nviol);
+__device__ void revisit_chunk(const SweepArgs<TX> &a, const double *Pl, int64_t ch, uint32_t T2,
+                              double &best, int32_t &bi, int32_t &bj, int32_t &nwin,
+                              int32_t &nviol) {
+    const int lane = threadIdx.x & 63;
+    TX r2[4];
+    plain_r2<K, TX>(a.S, a.pcols, a.n, a.Pr, ch * kChunk + lane * 4, r2);
+#pragma unroll 1
+    for (int e = 0; e < 4; ++e) {   // rolled: one copy of the FP64 evaluation
+        const TX re = e == 0 ? r2[0] : e == 1 ? r2[1] : e == 2 ? r2[2] : r2[3];
+        uint64_t cm = __ballot(key_of<TX>(re) <= T2);
+        while (cm) {
+            const int ln = __builtin_ctzll(cm);
+            cm &= cm - 1;
+            int64_t i, j;
+            decode_pair(ch * kChunk + ln * 4 + e, a.N, i, j);
+            const double r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, Pl, i, j);
+            const TX r2c = __shfl(re, ln, kWave);
+            ++nwin;
+            nviol += bound_broken(r, (double)r2c, a.e_abs, a.e_rel);
+            if (lex_less(r, (int32_t)i, (int32_t)j, best, bi, bj)) {
+                best = r; bi = (int32_t)i; bj = (int32_t)j;
+            }
+        }
+    }
+}
 
 // Selection (one block, after the pass): coarse minimum, window, FP64
 // rescoring, record.  Wavefront w of the block revisits the units that
 // wavefront slot w of each pass block produced, restricted to the pass
 // blocks whose minimum lies inside the window.  Returns the winning pair in
-// every thread (i < 0 if there is none).
-constexpr int kFlagCap = 512;   // flagged pass blocks listed in LDS (else a full scan)
+// every thread (i < 0 if there is none).  Every dependent global round trip
+// costs about a microsecond here, so each phase issues all of its loads
+// before it uses any.
+constexpr int kFlagCap = 512;        // flagged pass blocks listed in LDS (else a full scan)
+constexpr int kBlkVec = 8;           // uint4 loads of block minima per thread: npass <= 8192
+constexpr int kShortPerThread = 4;   // short-pair blocks per thread: <= 1024
 
 template <int K, typename TX, bool FUSED>
-__device__ int2 select_min(const SweepArgs<TX> &a, int nshort) {
+__device__ int2 select_min(const SweepArgs<TX> &a, int nshort, const double *Pl) {
     __shared__ int s_flag[kFlagCap];
     __shared__ int s_nflag;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // Code here runs once per launch on a cold instruction cache, so it is
-    // kept to compact loops rather than unrolled straight-line code.
-    // the short-pair partials (already FP64)
+    // per-block coarse minima (the array is padded with kKeyNone to a
+    // multiple of 4 x 256 entries) and the short-pair partials (FP64)
+    uint4 bm[kBlkVec];
+    const int nvec = (a.npass + 4 * kPairBlock - 1) / (4 * kPairBlock);
+#pragma unroll
+    for (int m = 0; m < kBlkVec; ++m)
+        bm[m] = m < nvec ? reinterpret_cast<const uint4 *>(a.blk_min)[threadIdx.x + m * kPairBlock]
+                         : make_uint4(kKeyNone, kKeyNone, kKeyNone, kKeyNone);
     double best = __builtin_huge_val();
     int32_t bi = 0x7fffffff, bj = 0x7fffffff, nres_short = 0;
-#pragma unroll 1
-    for (int sb = threadIdx.x; sb < nshort; sb += kPairBlock) {
-        const Partial p = a.spart[sb];
-        if (lex_less(p.r, p.i, p.j, best, bi, bj)) { best = p.r; bi = p.i; bj = p.j; }
-        nres_short += p.n_rescored;
+#pragma unroll
+    for (int m = 0; m < kShortPerThread; ++m) {
+        const int sb = (int)threadIdx.x + m * kPairBlock;
+        if (sb < nshort) {
+            const Partial p = a.spart[sb];
+            if (lex_less(p.r, p.i, p.j, best, bi, bj)) { best = p.r; bi = p.i; bj = p.j; }
+            nres_short += p.n_rescored;
+        }
     }
-    // global coarse minimum over the pass blocks
     uint32_t g = kKeyNone;
-#pragma unroll 1
-    for (int b = threadIdx.x; b < a.npass; b += 2 * kPairBlock) {
-        const uint32_t v0 = ld_u32(a.blk_min + b);
-        const uint32_t v1 = b + kPairBlock < a.npass ? ld_u32(a.blk_min + b + kPairBlock) : kKeyNone;
-        g = min(g, min(v0, v1));
-    }
+#pragma unroll
+    for (int m = 0; m < kBlkVec; ++m) g = min(g, min(min(bm[m].x, bm[m].y), min(bm[m].z, bm[m].w)));
     if (threadIdx.x == 0) s_nflag = 0;
     g = block_min_u32(g);
     double coarse, tr;
     const uint32_t T2 = window_key(g, a.e_abs, a.e_rel, &coarse, &tr);
-    // pass blocks whose minimum lies inside the window
+    // pass blocks whose minimum lies inside the window: a bit mask of the
+    // thread's 4 kBlkVec entries, then its set bits
     if (coarse >= 0.0) {
+        uint32_t fm = 0;
+#pragma unroll
+        for (int m = 0; m < kBlkVec; ++m)
+            fm |= (bm[m].x <= T2 ? 1u : 0u) << (4 * m) | (bm[m].y <= T2 ? 2u : 0u) << (4 * m) |
+                  (bm[m].z <= T2 ? 4u : 0u) << (4 * m) | (bm[m].w <= T2 ? 8u : 0u) << (4 * m);
 #pragma unroll 1
-        for (int b = threadIdx.x; b < a.npass; b += kPairBlock)
-            if (ld_u32(a.blk_min + b) <= T2) {
-                const int at = atomicAdd(&s_nflag, 1);
-                if (at < kFlagCap) s_flag[at] = b;
-            }
+        while (fm) {
+            const int bit = __builtin_ctz(fm);
+            fm &= fm - 1;
+            const int at = atomicAdd(&s_nflag, 1);
+            if (at < kFlagCap) s_flag[at] = 4 * ((int)threadIdx.x + (bit >> 2) * kPairBlock) + (bit & 3);
+        }
     }
     __syncthreads();
     const int nflag = s_nflag;
@@ -604,32 +694,54 @@ __device__ int2 select_min(const SweepArgs<TX> &a, int nshort) {
         // the result is a lexicographic minimum over the set
         const bool listed = nflag <= kFlagCap;
         const int nscan = listed ? nflag : a.npass;
+#pragma unroll 1
         for (int f = 0; f < nscan; ++f) {
             const int b = listed ? s_flag[f] : f;
-            if (!listed && ld_u32(a.blk_min + b) > T2) continue;
+            if (!listed && a.blk_min[b] > T2) continue;
             // the work items of wavefront slot wv of block b, 64 at a time
+#pragma unroll 1
             for (int64_t h0 = (int64_t)b * (kPairBlock / kWave) + wv; h0 < nunits_w; h0 += kWave * nw) {
                 const int64_t hl = h0 + lane * nw;
-                uint32_t um = kKeyNone;
+                uint32_t u0 = kKeyNone, u1 = kKeyNone, ag = 0;
                 if (hl < nunits_w) {
-                    if constexpr (FUSED) um = min(ld_u32(a.unit_min + 2 * hl), ld_u32(a.unit_min + 2 * hl + 1));
-                    else um = ld_u32(a.unit_min + hl);
-                }
-                uint64_t hits = __ballot(um <= T2);
-                while (hits) {
-                    const int64_t h = h0 + (int64_t)__builtin_ctzll(hits) * nw;
-                    hits &= hits - 1;
                     if constexpr (FUSED) {
-                        for (int x = 0; x < 2; ++x) {
-                            const int64_t u = 2 * h + x;
-                            if (ld_u32(a.unit_min + u) <= T2) {
+                        u0 = a.unit_min[2 * hl];
+                        u1 = a.unit_min[2 * hl + 1];
+                    } else {
+                        u0 = a.unit_min[hl];
+                        u1 = a.unit_min2[hl];
+                        ag = a.unit_arg[hl];
+                    }
+                }
+                uint64_t hits = __ballot((FUSED ? min(u0, u1) : u0) <= T2);
+                while (hits) {
+                    const int ln = __builtin_ctzll(hits);
+                    hits &= hits - 1;
+                    const int64_t h = h0 + (int64_t)ln * nw;
+                    const uint32_t v0 = __shfl(u0, ln, kWave), v1 = __shfl(u1, ln, kWave);
+                    if constexpr (FUSED) {
+#pragma unroll 1
+                        for (int x = 0; x < 2; ++x) {   // one call site
+                            if ((x == 0 ? v0 : v1) <= T2) {
                                 ++ntl;
-                                revisit_subtile<K, TX>(a, u, T2, best, bi, bj, nwin, nviol);
+                                revisit_subtile<K, TX>(a, Pl, 2 * h + x, T2, best, bi, bj, nwin, nviol);
                             }
                         }
                     } else {
                         ++ntl;
-                        revisit_chunk<K, TX>(a, h, T2, best, bi, bj, nwin, nviol);
+                        if (v1 > T2) {
+                            // the chunk's only window pair: rescore it directly
+                            int64_t i, j;
+                            decode_pair(h * kChunk + __shfl(ag, ln, kWave), a.N, i, j);
+                            const double r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, Pl, i, j);
+                            ++nwin;
+                            nviol += bound_broken(r, (double)__uint_as_float(v0), a.e_abs, a.e_rel);
+                            if (lex_less(r, (int32_t)i, (int32_t)j, best, bi, bj)) {
+                                best = r; bi = (int32_t)i; bj = (int32_t)j;
+                            }
+                        } else {
+                            revisit_chunk<K, TX>(a, Pl, h, T2, best, bi, bj, nwin, nviol);
+                        }
                     }
                 }
             }
@@ -667,34 +779,7 @@ __device__ int2 select_min(const SweepArgs<TX> &a, int nshort) {
     return f.r < __builtin_huge_val() ? make_int2(f.i, f.j) : make_int2(-1, -1);
 }
 
-template <int K, typename TX>
-__device__ void revisit_chunk(const SweepArgs<TX> &a, int64_t ch, uint32_t T2, double &best,
-                              int32_t &bi, int32_t &bj, int32_t &nwin, int32_t &nviol) {
-    const int lane = threadIdx.x & 63;
-    TX r2[4];
-    plain_r2<K, TX>(a.S, a.pcols, a.n, a.Pr, ch * kChunk + lane * 4, r2);
-#pragma unroll 1
-    for (int e = 0; e < 4; ++e) {   // rolled: one copy of the FP64 evaluation
-        const TX re = e == 0 ? r2[0] : e == 1 ? r2[1] : e == 2 ? r2[2] : r2[3];
-        uint64_t cm = __ballot(key_of<TX>(re) <= T2);
-        while (cm) {
-            const int ln = __builtin_ctzll(cm);
-            cm &= cm - 1;
-            int64_t i, j;
-            decode_pair(ch * kChunk + ln * 4 + e, a.N, i, j);
-            const double r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, a.P64t, i, j);
-            const TX r2c = __shfl(re, ln, kWave);
-            ++nwin;
-            nviol += bound_broken(r, (double)r2c, a.e_abs, a.e_rel);
-            if (lex_less(r, (int32_t)i, (int32_t)j, best, bi, bj)) {
-                best = r; bi = (int32_t)i; bj = (int32_t)j;
-            }
-        }
-    }
-}
-
-// The pass: blocks below npass score pairs coarsely, the others (fused
-// form) score the short pairs in FP64.  Every block writes its own result
+// The pass: every block scores its pairs coarsely and writes its own result
 // slot; the kernel boundary is the grid-wide barrier before selection.
 template <int K, typename TX, bool FUSED>
 __global__ __launch_bounds__(kPairBlock) void k_pass(SweepArgs<TX> a) {
@@ -704,8 +789,8 @@ __global__ __launch_bounds__(kPairBlock) void k_pass(SweepArgs<TX> a) {
     if (threadIdx.x == 0) a.blk_min[blockIdx.x] = best;
 }
 
-// Fused form, before the pass: Y = (X - mu) P (blocks below gemm_blocks) and,
-// in the same launch because they do not need Y, the FP64 scores of the
+// Fused form, before the pass: Y = (X - mu) P (blocks below gemm_blocks)
+// and, in the same grid because they need only P, the FP64 scores of the
 // short pairs (the other blocks).
 template <int K, typename TX>
 __global__ __launch_bounds__(kPairBlock) void k_prep(SweepArgs<TX> a, const double *__restrict__ mu,
@@ -829,8 +914,134 @@ __device__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
     }
 }
 
+// The same update with the vectors in registers, for n <= 64 M (lane l owns
+// components l + 64 m) and small K M: every operation of apply_update, in the
+// same order per vector, but without LDS round trips, and with the
+// independent inner products of one step (c = P^T s; the projections of all
+// later vectors on q_m) reduced together, so their latencies overlap.
+template <int K, int M, typename TX>
+__device__ void apply_update_reg(const TX *__restrict__ X, int64_t ldx, int n, const double *Pl,
+                                 double *__restrict__ P64t, double *__restrict__ P64r,
+                                 void *__restrict__ Pr, int pr_kind, double alpha, int rule,
+                                 DevResult *__restrict__ res, int64_t i, int64_t j) {
+    const int lane = threadIdx.x & 63;
+    double A[K][M], s[M], v[M];
+    double d2 = 0.0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int l = lane + 64 * m;
+        const bool in = l < n;
+        const int lc = in ? l : 0;
+        const double dl = in ? (double)X[i * ldx + lc] - (double)X[j * ldx + lc] : 0.0;
+        s[m] = dl;
+        d2 = __builtin_fma(dl, dl, d2);
+#pragma unroll
+        for (int q = 0; q < K; ++q) A[q][m] = in ? Pl[q * n + lc] : 0.0;
+    }
+    const double d = sqrt(wave_sum_fast(d2));
+#pragma unroll
+    for (int m = 0; m < M; ++m) s[m] = s[m] / d;
+    double c[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        c[q] = 0.0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) c[q] = __builtin_fma(A[q][m], s[m], c[q]);
+    }
+    wave_sum_many<K>(c);
+    int t = 0;
+    double cmax = -1.0;
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+        if (fabs(c[q]) > cmax) { cmax = fabs(c[q]); t = q; }
+    if (lane == 0) res->t = t;
+    if (cmax == 0.0) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) A[0][m] = s[m];
+    } else {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc = __builtin_fma(A[q][m], c[q], acc);
+            v[m] = acc;
+        }
+        // MGS input order (v, p_1..p_{t-1}, p_{t+1}..p_k): rows 1..t take
+        // rows 0..t-1 (selects, no dynamic register indexing)
+#pragma unroll
+        for (int q = K - 1; q >= 1; --q)
+#pragma unroll
+            for (int m = 0; m < M; ++m) A[q][m] = q <= t ? A[q - 1][m] : A[q][m];
+#pragma unroll
+        for (int m = 0; m < M; ++m) A[0][m] = v[m];
+        double vnorm = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < K; ++mm) {
+            double nn = 0.0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) nn = __builtin_fma(A[mm][m], A[mm][m], nn);
+            const double nrm = sqrt(wave_sum_fast(nn));
+            if (mm == 0) vnorm = nrm;
+#pragma unroll
+            for (int m = 0; m < M; ++m) A[mm][m] = A[mm][m] / nrm;
+            double dots[K];
+#pragma unroll
+            for (int jv = 0; jv < K; ++jv) {
+                dots[jv] = 0.0;
+                if (jv > mm) {
+#pragma unroll
+                    for (int m = 0; m < M; ++m) dots[jv] = __builtin_fma(A[mm][m], A[jv][m], dots[jv]);
+                }
+            }
+            wave_sum_many<K>(dots, mm + 1);
+#pragma unroll
+            for (int jv = mm + 1; jv < K; ++jv)
+#pragma unroll
+                for (int m = 0; m < M; ++m) A[jv][m] = A[jv][m] - dots[jv] * A[mm][m];
+        }
+        double wn = 1.0;
+        if (rule == SAP_STEP_NORMALIZED) {
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const double w = s[m] - v[m];
+                acc = __builtin_fma(w, w, acc);
+            }
+            wn = sqrt(wave_sum_fast(acc));
+        }
+        double un = 0.0;
+        double u[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            if (rule == SAP_STEP_NORMALIZED)
+                u[m] = (1.0 - alpha) * (v[m] / vnorm) + (wn > 0.0 ? alpha * ((s[m] - v[m]) / wn) : 0.0);
+            else
+                u[m] = (1.0 - alpha) * v[m] + alpha * (s[m] - v[m]);
+            un = __builtin_fma(u[m], u[m], un);
+        }
+        const double unrm = sqrt(wave_sum_fast(un));
+#pragma unroll
+        for (int m = 0; m < M; ++m) A[0][m] = u[m] / unrm;
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int l = lane + 64 * m;
+        if (l < n) {
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const double pv = A[q][m];
+                P64t[(int64_t)q * n + l] = pv;
+                P64r[(int64_t)l * K + q] = pv;
+                if (pr_kind == 1) static_cast<float *>(Pr)[(int64_t)l * K + q] = (float)pv;
+                else if (pr_kind == 2) static_cast<double *>(Pr)[(int64_t)l * K + q] = pv;
+            }
+        }
+    }
+}
+
 // Selection, record and (do_step) update, in one block.  Dynamic LDS holds
-// the update's vectors: (K + 2) n + 16 doubles.
+// P (read by the rescoring, then the update's working copy) and the update's
+// vectors: (K + 2) n + 16 doubles.
 template <int K, typename TX, bool FUSED>
 __global__ __launch_bounds__(kPairBlock) void k_select(SweepArgs<TX> a, int nshort,
                                                        double *__restrict__ P64t,
@@ -838,13 +1049,23 @@ __global__ __launch_bounds__(kPairBlock) void k_select(SweepArgs<TX> a, int nsho
                                                        void *__restrict__ Pr, int pr_kind,
                                                        double alpha, int rule, int do_step) {
     extern __shared__ double sm_dyn[];
-    // P into LDS now, so that its loads overlap the selection
-    if (do_step)
-        for (int e = threadIdx.x; e < K * a.n; e += kPairBlock) sm_dyn[e] = a.P64t[e];
-    const int2 ij = select_min<K, TX, FUSED>(a, nshort);
-    if (do_step && ij.x >= 0 && threadIdx.x < kWave)
-        apply_update<K, TX>(a.X, a.ldx, a.n, P64t, P64r, Pr, pr_kind, alpha, rule, a.res, ij.x,
-                            ij.y, sm_dyn);
+    // P into LDS now, so that its loads overlap the first phase (the block
+    // barriers inside select_min order these writes before any read)
+    for (int e = threadIdx.x; e < K * a.n; e += kPairBlock) sm_dyn[e] = a.P64t[e];
+    const int2 ij = select_min<K, TX, FUSED>(a, nshort, sm_dyn);
+    if (do_step && ij.x >= 0 && threadIdx.x < kWave) {
+        // registers when K ceil(n/64) is small (one 64-lane slice of each
+        // vector, or two for K <= 6), LDS otherwise
+        if (K <= 8 && a.n <= 64)
+            apply_update_reg<K, 1, TX>(a.X, a.ldx, a.n, sm_dyn, P64t, P64r, Pr, pr_kind, alpha, rule,
+                                       a.res, ij.x, ij.y);
+        else if (K <= 6 && a.n <= 128)
+            apply_update_reg<K, 2, TX>(a.X, a.ldx, a.n, sm_dyn, P64t, P64r, Pr, pr_kind, alpha, rule,
+                                       a.res, ij.x, ij.y);
+        else
+            apply_update<K, TX>(a.X, a.ldx, a.n, P64t, P64r, Pr, pr_kind, alpha, rule, a.res, ij.x,
+                                ij.y, sm_dyn);
+    }
 }
 
 // ------------------------------------------------------------------ small helpers
