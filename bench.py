@@ -147,6 +147,9 @@ def main():
                     help="budget of the FP64 CPU oracle baseline (0 disables it)")
     ap.add_argument("--softmin-steps", type=int, default=20,
                     help="timed soft-min optimisation steps on the hyperspectral workload (0 disables)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy a MIB-MiB device buffer 3 times (a kernel of known traffic, "
+                         "to scale rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -164,8 +167,17 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    w = sap_inputs.make("trig64")
     dev = torch.device("cuda:0")
+    if args.calibrate_copy > 0:
+        nb = args.calibrate_copy * (1 << 20)
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {nb} bytes")
+        del src, dst
+    w = sap_inputs.make("trig64")
     X = torch.from_numpy(w.X).to(dev)
     P0 = torch.from_numpy(w.P0)
     forms = [f for f in args.forms.split(",") if f]

@@ -31,6 +31,7 @@ struct sap_ctx {
 
     const void *X = nullptr;
     int64_t ldx = 0, N = 0, p = 0;
+    bool vec_x = false, vec_p = false;   // 16-byte loads of X rows / P64t rows are aligned
     int n = 0, k = 0, kp = 0;
 
     // fused
@@ -39,7 +40,7 @@ struct sap_ctx {
     float4 *d_invd2 = nullptr;
     float *d_Y = nullptr;
     int2 *d_close = nullptr;
-    double *d_cdiff = nullptr, *d_cd = nullptr;   // short pairs: x_i - x_j (one row each), ||.||
+    double *d_cd = nullptr;   // short pairs: ||x_i - x_j||
     // the short-pair list (sorted by (i, j)) as CSR by i and by j
     int32_t *d_rp_i = nullptr, *d_rp_j = nullptr, *d_permj = nullptr;
 
@@ -57,7 +58,7 @@ struct sap_ctx {
     DevState *d_st = nullptr;
     Partial *d_part = nullptr;
     DevResult *d_res = nullptr;
-    int pass_grid = 0, short_grid = 0, short_group = 8;
+    int pass_grid = 0, short_grid = 0;
     uint32_t *d_blk = nullptr;   // per pass block minimum
     size_t tail_lds = 0;
 
@@ -381,18 +382,17 @@ static sap_status init_fused(sap_ctx *h) {
         SAP_HIP(h, hipMemcpyAsync(h->d_permj, permj.data(), sizeof(int32_t) * want, hipMemcpyHostToDevice, h->stream));
         // the host vectors must outlive the asynchronous copies
         SAP_HIP(h, hipStreamSynchronize(h->stream));
-        SAP_TRY(dalloc(h, &h->d_cdiff, sizeof(double) * (size_t)h->n * want));
         SAP_TRY(dalloc(h, &h->d_cd, sizeof(double) * (size_t)want));
         const unsigned gblk = (unsigned)ceil_div(want, 256);
         if (h->cfg.dtype == SAP_F64)
-            hipLaunchKernelGGL(k_short_diffs<double>, dim3(gblk), dim3(256), 0, h->stream,
+            hipLaunchKernelGGL(k_short_len<double>, dim3(gblk), dim3(256), 0, h->stream,
                                static_cast<const double *>(h->X), h->ldx, h->n, h->d_close, want,
-                               h->d_cdiff, h->d_cd);
+                               h->d_cd);
         else
-            hipLaunchKernelGGL(k_short_diffs<float>, dim3(gblk), dim3(256), 0, h->stream,
+            hipLaunchKernelGGL(k_short_len<float>, dim3(gblk), dim3(256), 0, h->stream,
                                static_cast<const float *>(h->X), h->ldx, h->n, h->d_close, want,
-                               h->d_cdiff, h->d_cd);
-        SAP_LAUNCHED(h, "k_short_diffs");
+                               h->d_cd);
+        SAP_LAUNCHED(h, "k_short_len");
     }
     h->nclose = want;
     // every pair left to the coarse pass has fl32(1/d^2) <= w_max, hence
@@ -402,9 +402,9 @@ static sap_status init_fused(sap_ctx *h) {
     h->close_d = dtarget * std::pow(2.0, -msel / 4.0);
     h->e_abs = st.keep_max ? 2.0 * delta * std::sqrt((double)wmax * (1.0 + std::ldexp(1.0, -22))) : 0.0;
     h->e_rel = (h->k + 4) * kU32;
-    h->pass_grid = (int)std::min<int64_t>(ceil_div(2 * h->ntiles, 4), 8192);   // 4 half-tiles per block
-    h->short_group = 8;
-    while (h->short_group < 64 && h->short_group * 8 < h->n) h->short_group *= 2;
+    // at least two half-tiles per wavefront (the next one's loads overlap the
+    // current one's arithmetic), four wavefronts per block
+    h->pass_grid = (int)std::min<int64_t>(ceil_div(2 * h->ntiles, 8), 8192);
     // iteration: 64 short pairs per block (16 per wavefront, on the matrix
     // cores); the soft-min's short-pair blocks use the same grid size
     h->short_grid = h->nclose > 0 ? (int)std::min<int64_t>(ceil_div(h->nclose, 64), 1024) : 0;
@@ -457,15 +457,15 @@ static SweepArgs<TX> sweep_args(sap_ctx *h, double *tr_min, int64_t *tr_ij, int3
     a.unit_arg = h->d_targ;
     a.blk_min = h->d_blk;
     a.close = h->d_close;
-    a.cdiff = h->d_cdiff;
     a.cd = h->d_cd;
     a.nclose = h->nclose;
-    a.group = h->short_group;
     a.spart = h->d_part;
     a.e_abs = h->e_abs;
     a.e_rel = h->e_rel;
     a.X = static_cast<const TX *>(h->X);
     a.ldx = h->ldx;
+    a.vx = h->vec_x;
+    a.vp = h->vec_p;
     a.N = h->N;
     a.P64t = h->d_P64t;
     a.gmin_out = &h->d_st->gmin;
@@ -487,16 +487,15 @@ static sap_status launch_iteration(sap_ctx *h, int do_step, double *tr_min, int6
     const int nshort = fused ? h->short_grid : 0;
     const dim3 blk(kPairBlock);
     if (fused) {
-        const int gemm_blocks = (int)(h->Npad / 64);
-        const dim3 g0((unsigned)(gemm_blocks + nshort));
+        const dim3 g0((unsigned)(h->Npad / 64));
         SAP_DISPATCH_K(K, SAP_TRY(launch(h, 0, "k_prep", k_prep<K, TX>, g0, blk, 0, a, h->d_mu,
-                                         h->d_Y, h->Npad, gemm_blocks)));
+                                         h->d_Y, h->Npad)));
     }
-    const dim3 g1((unsigned)h->pass_grid);
+    const dim3 g1((unsigned)(h->pass_grid + nshort));
     if (fused) {
-        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 1, "k_pass", k_pass<K, TX, true>, g1, blk, 0, a)));
+        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 1, "k_pass", k_pass<K, TX, true>, g1, blk, 0, a, nshort)));
     } else {
-        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 1, "k_pass", k_pass<K, TX, false>, g1, blk, 0, a)));
+        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 1, "k_pass", k_pass<K, TX, false>, g1, blk, 0, a, 0)));
     }
     const int pr_kind = fused ? 0 : (h->cfg.dtype == SAP_F64 ? 2 : 1);
     const uint32_t lds = (uint32_t)h->tail_lds;
@@ -586,11 +585,11 @@ static SmArgs sm_args(sap_ctx *h, double tau) {
     a.npass = h->pass_grid;
     a.n = h->n;
     a.close = h->d_close;
-    a.cdiff = h->d_cdiff;
     a.cd = h->d_cd;
     a.nclose = h->nclose;
-    a.group = h->short_group;
     a.P64t = h->d_smP64t;
+    a.vx = h->vec_x;
+    a.vp = h->vec_p;
     a.tau = tau;
     a.c2 = (float)(1.4426950408889634 / tau);   // log2(e) / tau
     a.part = h->d_smpart;
@@ -642,8 +641,8 @@ static sap_status sm_backward(sap_ctx *h, double tau, const float *grad_loss, fl
     SAP_TRY(launch(h, 5, "k_sm_grad", k_sm_grad<TX>, dim3((unsigned)h->sm_chunks, slices), dim3(256), 0,
                    X, h->ldx, h->N, h->n, K, (const double *)h->d_mu, (const double *)h->d_smZ,
                    h->sm_rows, h->d_smG));
-    SAP_TRY(launch(h, 5, "k_sm_dP", k_sm_dP, dim3(slices), dim3(256), 0, (const double *)h->d_smG,
-                   h->sm_chunks, h->n, K, grad_loss, dP));
+    SAP_TRY(launch(h, 5, "k_sm_dP", k_sm_dP, dim3((unsigned)ceil_div((int64_t)h->n * K, 64)), dim3(256), 0,
+                   (const double *)h->d_smG, h->sm_chunks, h->n, K, grad_loss, dP));
     return SAP_OK;
 }
 
@@ -664,6 +663,11 @@ sap_status sap_init(const sap_config *cfg, const void *X, int64_t ldx, const dou
     h->k = cfg->k;
     h->kp = cfg->k;
     h->p = cfg->N * (cfg->N - 1) / 2;
+    {
+        const size_t es = cfg->dtype == SAP_F64 ? 8 : 4;
+        h->vec_x = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && ((size_t)ldx * es) % 16 == 0;
+        h->vec_p = cfg->n % 2 == 0;
+    }
     h->stream = static_cast<hipStream_t>(stream);
     auto bail = [&](sap_status s) {
         g_tls_err = h->err.empty() ? g_tls_err : h->err;

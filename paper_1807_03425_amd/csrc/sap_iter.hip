@@ -5,13 +5,13 @@
 //   update    argmax basis vector, modified Gram-Schmidt, alpha shift.
 // Here it runs as three launches (two for the plain form):
 //   k_prep    (fused form) Y = (X - mu) P in FP64 on the matrix cores, rounded
-//             to FP32, and in the same grid the FP64 scores of the short
-//             pairs (too short for the coarse error bound), also on the
-//             matrix cores: P^T (x_i - x_j) from stored differences;
+//             to FP32;
 //   k_pass    the coarse FP32 score of every pair, reduced to per-unit and
 //             per-block minima (fused: ||y_i - y_j||^2 / d^2 per 16 x 64
 //             sub-tile; plain: ||P^T s||^2 per 256-pair chunk, with the
-//             chunk's argmin and second-smallest score);
+//             chunk's argmin and second-smallest score); in the fused form
+//             the same grid scores the short pairs (too short for the coarse
+//             error bound) in FP64 on the matrix cores;
 //   k_select  one block: global coarse minimum, the proven rescoring window,
 //             FP64 rescoring of every in-window pair, the FP64 (min, i, j)
 //             record, then the FP64 update of P by one wavefront.
@@ -88,17 +88,49 @@ __device__ __forceinline__ void wave_sum_many(double (&v)[NV], int from = 0) {
 
 // ------------------------------------------------------------------ GEMM
 
+// 16 consecutive elements p[0..15] as FP64 (exact for FP32): 16-byte vector
+// loads when vec (the caller guarantees p is 16-byte aligned), else scalar.
+__device__ __forceinline__ void load16(const float *__restrict__ p, bool vec, double (&o)[16]) {
+    if (vec) {
+        const float4 *q = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float4 t = q[u];
+            o[4 * u] = t.x; o[4 * u + 1] = t.y; o[4 * u + 2] = t.z; o[4 * u + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) o[u] = p[u];
+    }
+}
+__device__ __forceinline__ void load16(const double *__restrict__ p, bool vec, double (&o)[16]) {
+    if (vec) {
+        const double2 *q = reinterpret_cast<const double2 *>(p);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double2 t = q[u];
+            o[2 * u] = t.x; o[2 * u + 1] = t.y;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) o[u] = p[u];
+    }
+}
+
 // Y[r][c] = fl32( sum_l (x_rl - mu_l) P_lc ), rows >= N and columns >= k set
 // to 0.  One wavefront per 16-row block; v_mfma_f64_16x16x4_f64 with
 //   A (16 x 4):  lane = row + 16 * kk   (row = lane % 16, kk = lane / 16)
 //   B (4 x 16):  lane = col + 16 * kk
 //   D (16 x 16): lane holds rows lane/16 + 4 v, v = 0..3, column lane % 16
 //                (measured on gfx950 with an in-bounds probe of the builtin).
-// The operand loads of a 64-column chunk are issued before its 16 MFMAs.
+// In a 64-component chunk, k-slot kk of MFMA s carries component
+// l0 + 16 kk + s, so each lane reads 16 consecutive components of its row
+// (and of P's column): 16-byte loads when vx (X rows 16-byte aligned) and vp
+// (n even).  Every operand load of a chunk is issued before its 16 MFMAs.
 template <typename TX>
 __device__ void gemm_block(const TX *__restrict__ X, int64_t ldx, int64_t N, int n, int k,
                            const double *__restrict__ mu, const double *__restrict__ P64t,
-                           float *__restrict__ Y, int kp, int64_t Npad) {
+                           float *__restrict__ Y, int kp, int64_t Npad, bool vx, bool vp) {
     const int lane = threadIdx.x & 63;
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
     if (row0 >= Npad) return;
@@ -114,18 +146,14 @@ __device__ void gemm_block(const TX *__restrict__ X, int64_t ldx, int64_t N, int
     double4_t acc = {0.0, 0.0, 0.0, 0.0};
     int l0 = 0;
     for (; l0 + 64 <= n; l0 += 64) {
-        TX xa[16];
-        double ma[16], pb[16];
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int l = l0 + 4 * s + kk;
-            xa[s] = xr[l];
-            ma[s] = mu[l];
-            pb[s] = pc[l];
-        }
+        double xa[16], ma[16], pb[16];
+        const int lb = l0 + 16 * kk;
+        load16(xr + lb, vx, xa);
+        load16(mu + lb, true, ma);
+        load16(pc + lb, vp, pb);
 #pragma unroll
         for (int s = 0; s < 16; ++s)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(((double)xa[s] - ma[s]) * rmask, pb[s] * pmask,
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64((xa[s] - ma[s]) * rmask, pb[s] * pmask,
                                                        acc, 0, 0, 0);
     }
     for (; l0 < n; l0 += 4) {
@@ -357,16 +385,15 @@ struct SweepArgs {
     uint32_t *unit_arg;  // plain: position (0..255) of the chunk's smallest key
     uint32_t *blk_min;   // per pass block
     // short pairs (fused)
-    const int2 *close;
-    const double *cdiff;  // nclose x n, one contiguous difference vector per pair
-    const double *cd;     // their lengths
+    const int2 *close;    // short pairs (i, j), sorted
+    const double *cd;     // their lengths ||x_i - x_j||
     int64_t nclose;
-    int group;            // lanes per short pair (8, 16, 32 or 64)
     Partial *spart;       // per short-pair block
     // selection
     double e_abs, e_rel;
     const TX *X;
     int64_t ldx, N;
+    int vx, vp;           // 16-byte loads: X rows aligned; n even (rows of P64t)
     const double *P64t;
     uint32_t *gmin_out;
     DevResult *res;
@@ -376,46 +403,63 @@ struct SweepArgs {
     int it;
 };
 
-// Fused pass block.  One wavefront per half-tile h = 2 t + half (rows
-// 64 bi + 32 half .. +31 against the 64 columns of tile t = (bi, bj);
-// grid-stride over the pass blocks).  Every load of a half-tile is issued
-// up front: its 8 weight float4 per lane, the lane's y_j, and the 32 y_i
-// rows, copied into the wavefront's own LDS slice (read back as broadcasts;
-// no other wavefront touches the slice, so no barrier is needed).
+// Fused pass block pb.  Wavefront w = 4 pb + slot takes half-tiles
+// h = w, w + nw, ... (h = 2 t + half: rows 64 bi + 32 half .. +31 against the
+// 64 columns of tile t = (bi, bj)).  Before scoring a half-tile it issues
+// every load of the next one (8 weight float4 per lane, the lane's y_j, its
+// share of the 32 y_i rows), so memory latency overlaps the arithmetic; the
+// y_i rows go through the wavefront's own LDS slice (read back as
+// broadcasts; no other wavefront touches it, so no block barrier).
 // Per pair: K subtractions, K FMAs, one multiply, one unsigned min.
 template <int K, typename TX>
-__device__ uint32_t fused_pass_block(const SweepArgs<TX> &a) {
+__device__ uint32_t fused_pass_block(const SweepArgs<TX> &a, int pb) {
     __shared__ float4 s_y[kPairBlock / kWave][32 * kMaxK / 4];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t wid = (int64_t)blockIdx.x * (kPairBlock / kWave) + wv;
     const int64_t nw = (int64_t)a.npass * (kPairBlock / kWave);
     const int kp = a.kp;
     float4 *yl = s_y[wv];
-    const int nf4 = 8 * kp;   // float4 count of 32 rows of Y
+    const int nf4 = 8 * kp;                  // float4 count of 32 rows of Y (<= 128)
     uint32_t best = kKeyNone;
-    for (int64_t h = wid; h < a.nhalf; h += nw) {
-        const int64_t t = h >> 1;
-        const int half = (int)(h & 1);
+    int64_t h = (int64_t)pb * (kPairBlock / kWave) + wv;
+    // loads of half-tile h: weights, y_j, and two float4 of the y_i rows per lane
+    float4 w[8], yr0, yr1;
+    float yj[K];
+    auto fetch = [&](int64_t hh) {
+        const int64_t t = hh >> 1;
+        const int half = (int)(hh & 1);
         const float4 *tp = a.invd2 + t * (kTileElems / 4) + half * 512 + lane;
-        float4 w[8];
 #pragma unroll
         for (int g = 0; g < 8; ++g) w[g] = tp[g * 64];
         const int2 b = a.tiles[t];
         const float4 *ysrc =
             reinterpret_cast<const float4 *>(a.Y + ((int64_t)b.x * kTile + 32 * half) * kp);
-        for (int f = lane; f < nf4; f += kWave) yl[f] = ysrc[f];
-        float yj[K];
+        yr0 = ysrc[lane < nf4 ? lane : 0];
+        yr1 = ysrc[lane + 64 < nf4 ? lane + 64 : 0];
         load_yj<K>(a.Y, kp, (int64_t)b.y * kTile + lane, yj);
+    };
+    if (h < a.nhalf) fetch(h);
+    for (; h < a.nhalf; h += nw) {
+        float4 wc[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) wc[g] = w[g];
+        float yc[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) yc[c] = yj[c];
+        __builtin_amdgcn_wave_barrier();
+        if (lane < nf4) yl[lane] = yr0;
+        if (lane + 64 < nf4) yl[lane + 64] = yr1;
+        __builtin_amdgcn_wave_barrier();
+        if (h + nw < a.nhalf) fetch(h + nw);     // next half-tile's loads in flight
         const float *yi0 = reinterpret_cast<const float *>(yl);
         uint32_t m0 = kKeyNone, m1 = kKeyNone;
 #pragma unroll
         for (int g = 0; g < 8; ++g) {
             const float *yi = yi0 + 4 * g * kp;
-            uint32_t m = min(__float_as_uint(pair_r2<K>(yi, yj, w[g].x)),
-                             __float_as_uint(pair_r2<K>(yi + kp, yj, w[g].y)));
-            m = min(m, __float_as_uint(pair_r2<K>(yi + 2 * kp, yj, w[g].z)));
-            m = min(m, __float_as_uint(pair_r2<K>(yi + 3 * kp, yj, w[g].w)));
+            uint32_t m = min(__float_as_uint(pair_r2<K>(yi, yc, wc[g].x)),
+                             __float_as_uint(pair_r2<K>(yi + kp, yc, wc[g].y)));
+            m = min(m, __float_as_uint(pair_r2<K>(yi + 2 * kp, yc, wc[g].z)));
+            m = min(m, __float_as_uint(pair_r2<K>(yi + 3 * kp, yc, wc[g].w)));
             if (g < 4) m0 = min(m0, m); else m1 = min(m1, m);
         }
 #pragma unroll
@@ -429,16 +473,17 @@ __device__ uint32_t fused_pass_block(const SweepArgs<TX> &a) {
             a.unit_min[2 * h + 1] = m1;
         }
         best = min(best, min(m0, m1));
+        __builtin_amdgcn_wave_barrier();
     }
     return block_min_u32(best);
 }
 
 // Plain pass block: one wavefront per 256-pair chunk (grid-stride).
 template <int K, typename TX>
-__device__ uint32_t plain_pass_block(const SweepArgs<TX> &a) {
+__device__ uint32_t plain_pass_block(const SweepArgs<TX> &a, int pb) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t wid = (int64_t)blockIdx.x * (kPairBlock / kWave) + wv;
+    const int64_t wid = (int64_t)pb * (kPairBlock / kWave) + wv;
     const int64_t nw = (int64_t)a.npass * (kPairBlock / kWave);
     uint32_t best = kKeyNone;
     for (int64_t ch = wid; ch < a.nchunks; ch += nw) {
@@ -474,61 +519,79 @@ __device__ uint32_t plain_pass_block(const SweepArgs<TX> &a) {
     return block_min_u32(best);
 }
 
-// Short pairs in FP64 on the matrix cores: c = P^T (x_i - x_j) for every
-// pair, from the pairs' difference vectors (one row of n each), tiled exactly as gemm_block
-// (16 pairs per wavefront, grid-stride over groups of 16).  In the output
-// layout the 16 lanes of a DPP row hold the K (<= 16) components of one
-// pair's c, so ||c||^2 is four in-row DPP steps.  r = ||c|| / d, reduced to
-// the block's lexicographic (r, i, j) minimum.
+// c = P^T (x_i - x_j) for 16 short pairs in FP64 on the matrix cores, tiled
+// exactly as gemm_block; lane (m = lane % 16, kk = lane / 16) passes pair m
+// (pr, rin: whether it exists) and gets back c[pair kk + 4 v][component m]
+// in element v (0 for m >= K).  The A operand is the pair's difference
+// x_i - x_j formed from the two rows of X (exact in FP64 for FP32 inputs).
+template <int K, typename TX>
+__device__ __forceinline__ double4_t short_c16(const TX *__restrict__ X, int64_t ldx, int2 pr,
+                                               bool rin, int n, const double *__restrict__ P64t,
+                                               bool vx, bool vp) {
+    const int lane = threadIdx.x & 63;
+    const int m = lane & 15, kk = lane >> 4;
+    const double pmask = m < K ? 1.0 : 0.0;
+    const double *pc = P64t + (int64_t)(m < K ? m : K - 1) * n;
+    const double rmask = rin ? 1.0 : 0.0;
+    const TX *xi = X + (int64_t)pr.x * ldx;
+    const TX *xj = X + (int64_t)pr.y * ldx;
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    int l0 = 0;
+    for (; l0 + 64 <= n; l0 += 64) {   // component l0 + 16 kk + q in k-slot kk of MFMA q
+        double xa[16], xb[16], pb[16];
+        const int lb = l0 + 16 * kk;
+        load16(xi + lb, vx, xa);
+        load16(xj + lb, vx, xb);
+        load16(pc + lb, vp, pb);
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64((xa[q] - xb[q]) * rmask, pb[q] * pmask, acc, 0, 0, 0);
+    }
+    for (; l0 < n; l0 += 4) {
+        const int l = l0 + kk;
+        const double x = (l < n && rin) ? (double)xi[l] - (double)xj[l] : 0.0;
+        const double p = (l < n && m < K) ? pc[l] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, p, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Sum over the 16 lanes of a DPP row (every lane of the row gets it).
+__device__ __forceinline__ double row_sum16(double v) {
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    return v + dpp_f64<0x140>(v);
+}
+
+// Short pairs of the iteration: r = ||c|| / d per pair (16 per wavefront,
+// grid-stride), reduced to the block's lexicographic (r, i, j) minimum.
 template <int K, typename TX>
 __device__ void short_block(const SweepArgs<TX> &a, int sb, int nshort) {
     const int lane = threadIdx.x & 63;
     const int m = lane & 15, kk = lane >> 4;
-    const int n = a.n;
     const int64_t ngroups = (a.nclose + 15) / 16;
-    const double pmask = m < K ? 1.0 : 0.0;
-    const double *pc = a.P64t + (int64_t)(m < K ? m : K - 1) * n;
     double best = __builtin_huge_val();
     int32_t bi = 0x7fffffff, bj = 0x7fffffff, cnt = 0;
     for (int64_t g16 = (int64_t)sb * (kPairBlock / kWave) + (threadIdx.x >> 6); g16 < ngroups;
          g16 += (int64_t)nshort * (kPairBlock / kWave)) {
+        // pair m's indices and length, loaded once; the rows of X follow
         const int64_t row = g16 * 16 + m;
         const bool rin = row < a.nclose;
-        const double rmask = rin ? 1.0 : 0.0;
-        const double *dr = a.cdiff + (rin ? row : a.nclose - 1) * n;
-        double4_t acc = {0.0, 0.0, 0.0, 0.0};
-        int l0 = 0;
-        for (; l0 + 64 <= n; l0 += 64) {
-            double xa[16], pb[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                xa[q] = dr[l0 + 4 * q + kk];
-                pb[q] = pc[l0 + 4 * q + kk];
-            }
-#pragma unroll
-            for (int q = 0; q < 16; ++q)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[q] * rmask, pb[q] * pmask, acc, 0, 0, 0);
-        }
-        for (; l0 < n; l0 += 4) {
-            const int l = l0 + kk;
-            const double x = (l < n && rin) ? dr[l] : 0.0;
-            const double p = (l < n && m < K) ? pc[l] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, p, acc, 0, 0, 0);
-        }
-        // lane holds c[row kk + 4 v][column m]
+        const int2 pr = a.close[rin ? row : a.nclose - 1];
+        const double dlen = a.cd[rin ? row : a.nclose - 1];
+        const double4_t acc = short_c16<K, TX>(a.X, a.ldx, pr, rin, a.n, a.P64t, a.vx, a.vp);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            double q2 = acc[v] * acc[v];
-            q2 += dpp_f64<0xB1>(q2);
-            q2 += dpp_f64<0x4E>(q2);
-            q2 += dpp_f64<0x141>(q2);
-            q2 += dpp_f64<0x140>(q2);
-            const int64_t e = g16 * 16 + kk + 4 * v;
+            const double q2 = row_sum16(acc[v] * acc[v]);
+            const int src = kk + 4 * v;          // the lane (m = src) that loaded this pair
+            const int pi = __shfl(pr.x, src, kWave), pj = __shfl(pr.y, src, kWave);
+            const double dv = __shfl(dlen, src, kWave);
+            const int64_t e = g16 * 16 + src;
             if (m == 0 && e < a.nclose) {
-                const double r = sqrt(q2) / a.cd[e];
-                const int2 pr = a.close[e];
+                const double r = sqrt(q2) / dv;
                 ++cnt;
-                if (lex_less(r, pr.x, pr.y, best, bi, bj)) { best = r; bi = pr.x; bj = pr.y; }
+                if (lex_less(r, pi, pj, best, bi, bj)) { best = r; bi = pi; bj = pj; }
             }
         }
     }
@@ -779,27 +842,31 @@ __device__ int2 select_min(const SweepArgs<TX> &a, int nshort, const double *Pl)
     return f.r < __builtin_huge_val() ? make_int2(f.i, f.j) : make_int2(-1, -1);
 }
 
-// The pass: every block scores its pairs coarsely and writes its own result
-// slot; the kernel boundary is the grid-wide barrier before selection.
+// The pass.  Fused form: the first nshort blocks score the short pairs in
+// FP64 (they need only P, and start first so that they run beside the
+// coarse blocks), the other npass blocks score every pair coarsely.  Every
+// block writes its own result slot; the kernel boundary is the grid-wide
+// barrier before selection.
 template <int K, typename TX, bool FUSED>
-__global__ __launch_bounds__(kPairBlock) void k_pass(SweepArgs<TX> a) {
+__global__ __launch_bounds__(kPairBlock) void k_pass(SweepArgs<TX> a, int nshort) {
+    if constexpr (FUSED) {
+        if ((int)blockIdx.x < nshort) {
+            short_block<K, TX>(a, (int)blockIdx.x, nshort);
+            return;
+        }
+    }
+    const int pb = (int)blockIdx.x - (FUSED ? nshort : 0);
     uint32_t best;
-    if constexpr (FUSED) best = fused_pass_block<K, TX>(a);
-    else best = plain_pass_block<K, TX>(a);
-    if (threadIdx.x == 0) a.blk_min[blockIdx.x] = best;
+    if constexpr (FUSED) best = fused_pass_block<K, TX>(a, pb);
+    else best = plain_pass_block<K, TX>(a, pb);
+    if (threadIdx.x == 0) a.blk_min[pb] = best;
 }
 
-// Fused form, before the pass: Y = (X - mu) P (blocks below gemm_blocks)
-// and, in the same grid because they need only P, the FP64 scores of the
-// short pairs (the other blocks).
+// Fused form, before the pass: Y = (X - mu) P.
 template <int K, typename TX>
 __global__ __launch_bounds__(kPairBlock) void k_prep(SweepArgs<TX> a, const double *__restrict__ mu,
-                                                     float *__restrict__ Y, int64_t Npad,
-                                                     int gemm_blocks) {
-    if ((int)blockIdx.x < gemm_blocks)
-        gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, a.P64t, Y, a.kp, Npad);
-    else
-        short_block<K, TX>(a, (int)blockIdx.x - gemm_blocks, (int)gridDim.x - gemm_blocks);
+                                                     float *__restrict__ Y, int64_t Npad) {
+    gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, a.P64t, Y, a.kp, Npad, a.vx, a.vp);
 }
 
 // ------------------------------------------------------------------ the update
@@ -920,7 +987,7 @@ __device__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
 // independent inner products of one step (c = P^T s; the projections of all
 // later vectors on q_m) reduced together, so their latencies overlap.
 template <int K, int M, typename TX>
-__device__ void apply_update_reg(const TX *__restrict__ X, int64_t ldx, int n, const double *Pl,
+__device__ __forceinline__ void apply_update_reg(const TX *__restrict__ X, int64_t ldx, int n, const double *Pl,
                                  double *__restrict__ P64t, double *__restrict__ P64r,
                                  void *__restrict__ Pr, int pr_kind, double alpha, int rule,
                                  DevResult *__restrict__ res, int64_t i, int64_t j) {
@@ -1054,13 +1121,10 @@ __global__ __launch_bounds__(kPairBlock) void k_select(SweepArgs<TX> a, int nsho
     for (int e = threadIdx.x; e < K * a.n; e += kPairBlock) sm_dyn[e] = a.P64t[e];
     const int2 ij = select_min<K, TX, FUSED>(a, nshort, sm_dyn);
     if (do_step && ij.x >= 0 && threadIdx.x < kWave) {
-        // registers when K ceil(n/64) is small (one 64-lane slice of each
-        // vector, or two for K <= 6), LDS otherwise
+        // registers when every vector fits one 64-lane slice and K is
+        // small, LDS otherwise
         if (K <= 8 && a.n <= 64)
             apply_update_reg<K, 1, TX>(a.X, a.ldx, a.n, sm_dyn, P64t, P64r, Pr, pr_kind, alpha, rule,
-                                       a.res, ij.x, ij.y);
-        else if (K <= 6 && a.n <= 128)
-            apply_update_reg<K, 2, TX>(a.X, a.ldx, a.n, sm_dyn, P64t, P64r, Pr, pr_kind, alpha, rule,
                                        a.res, ij.x, ij.y);
         else
             apply_update<K, TX>(a.X, a.ldx, a.n, P64t, P64r, Pr, pr_kind, alpha, rule, a.res, ij.x,
@@ -1090,19 +1154,18 @@ __global__ void k_P_out(const double *__restrict__ P64t, int n, int k, double *_
     out[e] = P64t[(int64_t)q * n + l];
 }
 
-// Difference vectors and lengths of the short pairs, once: cdiff[e*n + l] =
-// x_i[l] - x_j[l] in FP64 (exact for FP32 inputs), cd[e] = ||x_i - x_j||.
+// Lengths of the short pairs, once: cd[e] = ||x_i - x_j||, the differences
+// formed in FP64 (exact for FP32 inputs).
 template <typename TX>
-__global__ void k_short_diffs(const TX *__restrict__ X, int64_t ldx, int n,
-                              const int2 *__restrict__ close, int64_t nclose,
-                              double *__restrict__ cdiff, double *__restrict__ cd) {
+__global__ void k_short_len(const TX *__restrict__ X, int64_t ldx, int n,
+                            const int2 *__restrict__ close, int64_t nclose,
+                            double *__restrict__ cd) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nclose) return;
     const int2 pr = close[e];
     double d2 = 0.0;
     for (int l = 0; l < n; ++l) {
         const double dl = (double)X[(int64_t)pr.x * ldx + l] - (double)X[(int64_t)pr.y * ldx + l];
-        cdiff[e * n + l] = dl;
         d2 = __builtin_fma(dl, dl, d2);
     }
     cd[e] = sqrt(d2);

@@ -46,12 +46,11 @@ struct SmArgs {
     int n;
     // short pairs
     const int2 *close;
-    const double *cdiff;
     const double *cd;
     int64_t nclose;
-    int group;
     // parameters
     const double *P64t;    // soft-min P, k x n FP64
+    int vx, vp;            // 16-byte loads: X rows aligned; n even
     double tau;
     float c2;              // log2(e) / tau
     SmPart *part;          // npass + nshort partials (forward)
@@ -97,47 +96,44 @@ __global__ void k_sm_loadP(const float *__restrict__ P, int n, int k, double *__
     P64t[(int64_t)q * n + l] = (double)P[e];
 }
 
-// Short pairs in FP64, `group` lanes per pair.  Forward: (min, sum) partial
-// of the block.  Backward: a (y_i - y_j) per pair into zpair.
-template <int K>
-__device__ void sm_short_block(const SmArgs &a, int sb, int nshort, int bwd) {
-    const int G = a.group;
-    const int sub = threadIdx.x & (G - 1);
-    const int64_t gpb = kPairBlock / G;
-    const int64_t first = (int64_t)sb * gpb + threadIdx.x / G;
-    const int64_t stride = (int64_t)nshort * gpb;
-    const int n = a.n;
+// Short pairs in FP64 (c = P^T (x_i - x_j) on the matrix cores, 16 pairs per
+// wavefront, grid-stride).  Forward: the block's (min, sum) partial.
+// Backward: a (y_i - y_j) = exp(-(r - L)/tau) / (r d^2) c per pair into zpair
+// (lane m writes component m).
+template <int K, typename TX>
+__device__ void sm_short_block(const SmArgs &a, const TX *__restrict__ X, int64_t ldx, int sb,
+                               int nshort, int bwd) {
+    const int lane = threadIdx.x & 63;
+    const int m = lane & 15, kk = lane >> 4;
+    const int64_t ngroups = (a.nclose + 15) / 16;
     const double tau = a.tau;
     const double L = bwd ? *a.Lp : 0.0;
-    double m = 0.0, s = 0.0;
-    for (int64_t e = first; e < a.nclose; e += stride) {
-        const double *dv = a.cdiff + e * n;
-        double c[K];
+    double mm = 0.0, ss = 0.0;
+    for (int64_t g16 = (int64_t)sb * (kPairBlock / kWave) + (threadIdx.x >> 6); g16 < ngroups;
+         g16 += (int64_t)nshort * (kPairBlock / kWave)) {
+        const int64_t row = g16 * 16 + m;
+        const bool rin = row < a.nclose;
+        const int2 pr = a.close[rin ? row : a.nclose - 1];
+        const double dlen = a.cd[rin ? row : a.nclose - 1];
+        const double4_t acc = short_c16<K, TX>(X, ldx, pr, rin, a.n, a.P64t, a.vx, a.vp);
 #pragma unroll
-        for (int q = 0; q < K; ++q) c[q] = 0.0;
-        for (int l = sub; l < n; l += G) {
-            const double dl = dv[l];
-#pragma unroll
-            for (int q = 0; q < K; ++q) c[q] = __builtin_fma(a.P64t[(int64_t)q * n + l], dl, c[q]);
-        }
-        for (int o = 1; o < G; o <<= 1)
-#pragma unroll
-            for (int q = 0; q < K; ++q) c[q] += __shfl_xor(c[q], o, kWave);
-        double r2 = 0.0;
-#pragma unroll
-        for (int q = 0; q < K; ++q) r2 = __builtin_fma(c[q], c[q], r2);
-        const double d = a.cd[e];
-        const double r = sqrt(r2) / d;
-        if (!bwd) {
-            if (sub == 0) lse_merge(m, s, r, 1.0, tau);
-        } else {
-            const double coef = r > 0.0 ? exp(-(r - L) / tau) / (r * d * d) : 0.0;
-#pragma unroll
-            for (int q = 0; q < K; ++q)
-                if ((q & (G - 1)) == sub) a.zpair[e * K + q] = coef * c[q];
+        for (int v = 0; v < 4; ++v) {
+            const double q2 = row_sum16(acc[v] * acc[v]);
+            const int src = kk + 4 * v;          // the lane (m = src) that loaded this pair
+            const double d = __shfl(dlen, src, kWave);
+            const int64_t e = g16 * 16 + src;
+            if (e < a.nclose) {
+                const double r = sqrt(q2) / d;
+                if (!bwd) {
+                    if (m == 0) lse_merge(mm, ss, r, 1.0, tau);
+                } else if (m < K) {
+                    const double coef = r > 0.0 ? exp(-(r - L) / tau) / (r * d * d) : 0.0;
+                    a.zpair[e * K + m] = coef * acc[v];
+                }
+            }
         }
     }
-    if (!bwd) block_lse(m, s, tau, a.part + a.npass + sb);
+    if (!bwd) block_lse(mm, ss, tau, a.part + a.npass + sb);
 }
 
 // Blocks below gemm_blocks: Y = (X - mu) P; the others: short pairs.
@@ -148,9 +144,10 @@ __global__ __launch_bounds__(kPairBlock) void k_sm_prep(SmArgs a, const TX *__re
                                                         float *__restrict__ Y, int64_t Npad,
                                                         int gemm_blocks, int bwd) {
     if ((int)blockIdx.x < gemm_blocks)
-        gemm_block<TX>(X, ldx, N, a.n, K, mu, a.P64t, Y, a.kp, Npad);
+        gemm_block<TX>(X, ldx, N, a.n, K, mu, a.P64t, Y, a.kp, Npad, a.vx, a.vp);
     else
-        sm_short_block<K>(a, (int)blockIdx.x - gemm_blocks, (int)gridDim.x - gemm_blocks, bwd);
+        sm_short_block<K, TX>(a, X, ldx, (int)blockIdx.x - gemm_blocks, (int)gridDim.x - gemm_blocks,
+                              bwd);
 }
 
 __device__ __forceinline__ float comp4(const float4 &v, int r) {
@@ -351,12 +348,39 @@ __global__ __launch_bounds__(kPairBlock) void k_sm_zred(SmArgs a, int64_t nb, in
     for (int q = 0; q < K; ++q) z[q] = 0.0;
     const int64_t trow0 = b * nb - b * (b - 1) / 2;   // first tile of row b
     const int half = lane >> 5, rr = lane & 31;
-    for (int64_t bj = b + wv; bj < nb; bj += 4) {
+    // two tiles per step, all their loads issued before the adds
+    int64_t bj = b + wv;
+    for (; bj + 4 < nb; bj += 8) {
+        const float *z0 = a.Zr + (2 * (trow0 + bj - b) + half) * (int64_t)(K * 32) + rr;
+        const float *z1 = z0 + 8 * (int64_t)(K * 32);   // tile bj + 4 of the same row
+        float t0[K], t1[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) { t0[q] = z0[q * 32]; t1[q] = z1[q * 32]; }
+#pragma unroll
+        for (int q = 0; q < K; ++q) z[q] += (double)t0[q] + (double)t1[q];
+    }
+    for (; bj < nb; bj += 4) {
         const float *zp = a.Zr + (2 * (trow0 + bj - b) + half) * (int64_t)(K * 32) + rr;
 #pragma unroll
         for (int q = 0; q < K; ++q) z[q] += (double)zp[q * 32];
     }
-    for (int64_t bi = wv; bi <= b; bi += 4) {
+    int64_t bi = wv;
+    for (; bi + 4 <= b; bi += 8) {
+        const int64_t t0 = bi * nb - bi * (bi - 1) / 2 + (b - bi);
+        const int64_t bi1 = bi + 4;
+        const int64_t t1 = bi1 * nb - bi1 * (bi1 - 1) / 2 + (b - bi1);
+        const float *z0 = a.Zc + 2 * t0 * (int64_t)(K * 64) + lane;
+        const float *z1 = a.Zc + 2 * t1 * (int64_t)(K * 64) + lane;
+        float u0[K], u1[K], v0[K], v1[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            u0[q] = z0[q * 64]; v0[q] = z0[K * 64 + q * 64];
+            u1[q] = z1[q * 64]; v1[q] = z1[K * 64 + q * 64];
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) z[q] += ((double)u0[q] + (double)v0[q]) + ((double)u1[q] + (double)v1[q]);
+    }
+    for (; bi <= b; bi += 4) {
         const int64_t t = bi * nb - bi * (bi - 1) / 2 + (b - bi);
         const float *zp = a.Zc + 2 * t * (int64_t)(K * 64) + lane;
 #pragma unroll
@@ -404,15 +428,35 @@ __global__ __launch_bounds__(256) void k_sm_grad(const TX *__restrict__ X, int64
     Gpart[(int64_t)blockIdx.x * n * K + e] = acc;
 }
 
-// dP (n x k row-major FP32) = dL/dloss * sum over chunks, in chunk order.
-__global__ void k_sm_dP(const double *__restrict__ Gpart, int nchunks, int n, int K,
-                        const float *__restrict__ grad_loss, float *__restrict__ dP) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * K) return;
-    const int l = e % n, q = e / n;
+// dP (n x k row-major FP32) = dL/dloss * sum over the chunks: one block per
+// 64 output elements; its four wavefronts take every fourth chunk, with
+// eight loads in flight per lane, and their sums are added in a fixed order.
+__global__ __launch_bounds__(256) void k_sm_dP(const double *__restrict__ Gpart, int nchunks, int n,
+                                               int K, const float *__restrict__ grad_loss,
+                                               float *__restrict__ dP) {
+    __shared__ double sp[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
+    const int nk = n * K;
     double acc = 0.0;
-    for (int c = 0; c < nchunks; ++c) acc += Gpart[(int64_t)c * n * K + e];
-    dP[(int64_t)l * K + q] = (float)((double)grad_loss[0] * acc);
+    if (e < nk) {
+        int c = wv;
+        for (; c + 28 < nchunks; c += 32) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = Gpart[(int64_t)(c + 4 * u) * nk + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += t[u];
+        }
+        for (; c < nchunks; c += 4) acc += Gpart[(int64_t)c * nk + e];
+    }
+    sp[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && e < nk) {
+        const int l = e % n, q = e / n;
+        const double g = ((sp[0][lane] + sp[1][lane]) + sp[2][lane]) + sp[3][lane];
+        dP[(int64_t)l * K + q] = (float)((double)grad_loss[0] * g);
+    }
 }
 
 }  // namespace sap
