@@ -21,6 +21,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -36,6 +37,29 @@ VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: lane-instr
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pass_fused_trig64_N4000_n64_k6_traffic.txt")
+KERNEL_SOURCES = ("paper_1807_03425_amd/csrc/sap_iter.hip", "paper_1807_03425_amd/csrc/sap_common.h")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused pass, from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (scaled by a 256 MiB copy), if the kernel
+    sources still hash to what was profiled; otherwise None."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            lines = [l for l in f.read().splitlines() if l and not l.startswith("#") and ":" in l]
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in (l.split(":", 1) for l in lines)}
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    if kv.get("source_sha256") != h.hexdigest():
+        return None
+    return float(kv["traffic_bytes_per_launch"].split()[0])
 
 
 def time_form(torch, ctx, steps, warmup, prof_steps):
@@ -232,8 +256,9 @@ def main():
     head = "fused" if "fused" in sums else forms[0]
     hs = sums[head]
     pk = hs["pass_kernel"]
+    traffic = measured_traffic() if head == "fused" else None
     roofline = dict(bound="hbm", achieved=pk["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=(pk["gbs"] / HBM_PEAK_GBS) if pk["gbs"] else None, traffic=None,
+                    frac=(pk["gbs"] / HBM_PEAK_GBS) if pk["gbs"] else None, traffic=traffic,
                     kernel=f"sap::k_pass<{w.k}, float, {'true' if head == 'fused' else 'false'}>",
                     bytes_per_launch=pk["bytes_per_launch"],
                     avg_launch_us=pk["avg_us"], valu_frac=pk["valu_frac"])

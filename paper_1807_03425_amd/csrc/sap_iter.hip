@@ -313,19 +313,71 @@ __device__ __forceinline__ int bound_broken(double r, double r2c, double e_abs, 
     return fabs(r - rc) > (e_abs + e_rel * fmax(r, rc)) * 1.0001 ? 1 : 0;
 }
 
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ void lex_pick(double &r, int32_t &i, int32_t &j, double r2, int32_t i2,
+                                         int32_t j2) {
+    if (lex_less(r2, i2, j2, r, i, j)) { r = r2; i = i2; j = j2; }
+}
+
+template <int CTRL>
+__device__ __forceinline__ void lex_step_dpp(double &r, int32_t &i, int32_t &j) {
+    lex_pick(r, i, j, dpp_f64<CTRL>(r), dpp_i32<CTRL>(i), dpp_i32<CTRL>(j));
+}
+
+// Lexicographic (r, i, j) minimum over the wavefront, in every lane: the same
+// six exchange steps as wave_sum_fast (four DPP steps inside 16-lane rows,
+// then the permlane16 / permlane32 swaps, whose two results are the lane's
+// own tuple and its partner's, in either order: the minimum of the two does
+// not depend on that order).  No LDS traffic.
+__device__ __forceinline__ void wave_min_lex_fast(double &r, int32_t &i, int32_t &j) {
+    lex_step_dpp<0xB1>(r, i, j);
+    lex_step_dpp<0x4E>(r, i, j);
+    lex_step_dpp<0x141>(r, i, j);
+    lex_step_dpp<0x140>(r, i, j);
+    {
+        const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(r), __double2loint(r), false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(r), __double2hiint(r), false, false);
+        const auto ii = __builtin_amdgcn_permlane16_swap(i, i, false, false);
+        const auto jj = __builtin_amdgcn_permlane16_swap(j, j, false, false);
+        r = __hiloint2double(hi[0], lo[0]); i = ii[0]; j = jj[0];
+        lex_pick(r, i, j, __hiloint2double(hi[1], lo[1]), ii[1], jj[1]);
+    }
+    {
+        const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(r), __double2loint(r), false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(r), __double2hiint(r), false, false);
+        const auto ii = __builtin_amdgcn_permlane32_swap(i, i, false, false);
+        const auto jj = __builtin_amdgcn_permlane32_swap(j, j, false, false);
+        r = __hiloint2double(hi[0], lo[0]); i = ii[0]; j = jj[0];
+        lex_pick(r, i, j, __hiloint2double(hi[1], lo[1]), ii[1], jj[1]);
+    }
+}
+
+// Integer sum over the wavefront, in every lane (same exchange pattern).
+__device__ __forceinline__ int32_t wave_sum_i32_fast(int32_t v) {
+    v += dpp_i32<0xB1>(v);
+    v += dpp_i32<0x4E>(v);
+    v += dpp_i32<0x141>(v);
+    v += dpp_i32<0x140>(v);
+    const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = a[0] + a[1];
+    const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return b[0] + b[1];
+}
+
 // Block-wide reduction of a per-thread (r, i, j) and counters into *out
 // (written by thread 0).  All 256 threads must call it.
 __device__ void block_reduce_partial(double r, int32_t i, int32_t j, int32_t nres, int32_t ntl,
                                      int32_t nviol, Partial *out) {
     __shared__ Partial sb[kPairBlock / kWave];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    wave_min_lex(r, i, j);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        nres += __shfl_xor(nres, o, kWave);
-        ntl += __shfl_xor(ntl, o, kWave);
-        nviol += __shfl_xor(nviol, o, kWave);
-    }
+    wave_min_lex_fast(r, i, j);
+    nres = wave_sum_i32_fast(nres);
+    ntl = wave_sum_i32_fast(ntl);
+    nviol = wave_sum_i32_fast(nviol);
     if (lane == 0) sb[wv] = Partial{r, i, j, nres, ntl, nviol, 0};
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -343,9 +395,22 @@ __device__ void block_reduce_partial(double r, int32_t i, int32_t j, int32_t nre
     __syncthreads();
 }
 
+// Unsigned minimum over the wavefront, in every lane (same exchange pattern
+// as wave_sum_fast; the minimum of a swap's two results is order-free).
+__device__ __forceinline__ uint32_t wave_min_u32_fast(uint32_t v) {
+    v = min(v, (uint32_t)dpp_i32<0xB1>((int)v));
+    v = min(v, (uint32_t)dpp_i32<0x4E>((int)v));
+    v = min(v, (uint32_t)dpp_i32<0x141>((int)v));
+    v = min(v, (uint32_t)dpp_i32<0x140>((int)v));
+    const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = min((uint32_t)a[0], (uint32_t)a[1]);
+    const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return min((uint32_t)b[0], (uint32_t)b[1]);
+}
+
 __device__ __forceinline__ uint32_t block_min_u32(uint32_t v) {
     __shared__ uint32_t sm[kPairBlock / kWave];
-    v = wave_min_u32(v);
+    v = wave_min_u32_fast(v);
     if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
     __syncthreads();
     uint32_t b = sm[0];
@@ -462,12 +527,8 @@ __device__ uint32_t fused_pass_block(const SweepArgs<TX> &a, int pb) {
             m = min(m, __float_as_uint(pair_r2<K>(yi + 3 * kp, yc, wc[g].w)));
             if (g < 4) m0 = min(m0, m); else m1 = min(m1, m);
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const uint32_t x0 = __shfl_xor(m0, o, kWave), x1 = __shfl_xor(m1, o, kWave);
-            m0 = min(m0, x0);
-            m1 = min(m1, x1);
-        }
+        m0 = wave_min_u32_fast(m0);
+        m1 = wave_min_u32_fast(m1);
         if (lane == 0) {
             a.unit_min[2 * h] = m0;
             a.unit_min[2 * h + 1] = m1;

@@ -270,3 +270,32 @@ def test_large_workloads_sampled(name, k):
     r = r[np.isfinite(r)]
     assert r.min() >= res["min_norm"] - 1e-12
     ctx.close()
+
+
+@pytest.mark.parametrize("form", ["plain", "fused"])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_exact_ties_take_smallest_pair(form, dtype):
+    """Integer coordinates (exact in both dtypes) and P = the first two axes;
+    five translated copies of one short difference vector give pairs whose
+    FP64 r are bit-identical.  The minimum is that tie, and the reported pair
+    must be its lexicographically smallest (i, j), exactly as the oracle's."""
+    rng = np.random.default_rng(11)
+    N, n, k = 300, 8, 2
+    X = rng.integers(-50, 51, size=(N, n)).astype(np.float64)
+    # coordinate 0: distinct multiples of 4, so every other pair has
+    # |dx_0| >= 3 and a much shorter length than delta
+    X[:, 0] = 4.0 * rng.permutation(N)
+    delta = np.array([1, 0, 300, 400, 200, -100, 250, 350], dtype=np.float64)
+    for a, b in ((250, 260), (40, 290), (7, 8), (120, 5), (299, 150)):
+        X[b] = X[a] + delta
+    X = X.astype(dtype)
+    P0 = np.zeros((n, k))
+    P0[0, 0] = P0[1, 1] = 1.0
+    ref = oracle.min_secant(X, P0)
+    assert ref["r_second"] == ref["r_min"], "the planted tie is not the minimum"
+    ctx = SapContext(torch.from_numpy(X).to(DEV), torch.from_numpy(P0), form=form)
+    res = ctx.min_secant()
+    assert res["certified"] == 1
+    assert (res["i"], res["j"]) == (ref["i"], ref["j"]), (res, ref)
+    assert abs(res["min_norm"] - ref["r_min"]) <= min_tol(ref["r_min"], n, k)
+    ctx.close()
