@@ -53,13 +53,10 @@ struct sap_ctx {
     double *d_P64t = nullptr;
     double *d_P64r = nullptr;
     double *d_mu = nullptr;
-    uint32_t *d_tmin = nullptr;
-    uint32_t *d_tmin2 = nullptr, *d_targ = nullptr;   // plain: per-chunk second key, argmin
     DevState *d_st = nullptr;
-    Partial *d_part = nullptr;
+    Partial *d_part = nullptr;   // pass-block results, then one per short-pair block
     DevResult *d_res = nullptr;
     int pass_grid = 0, short_grid = 0;
-    uint32_t *d_blk = nullptr;   // per pass block minimum
     size_t tail_lds = 0;
 
     // soft-min (allocated on first use)
@@ -161,6 +158,14 @@ static sap_status validate(const sap_config *c, int64_t ldx, const void *X, cons
         return fail(nullptr, SAP_ERR_INVALID_ARG, "dtype must be SAP_F64 or SAP_F32");
     if (c->form != SAP_PLAIN && c->form != SAP_FUSED)
         return fail(nullptr, SAP_ERR_INVALID_ARG, "form must be SAP_PLAIN or SAP_FUSED");
+    {
+        // per-block records hold 32-bit pair (plain) or sub-tile (fused) indices
+        const int64_t p = c->N * (c->N - 1) / 2, nb = (c->N + kTile - 1) / kTile;
+        if (c->form == SAP_PLAIN && p >= (1ll << 32) - kChunk)
+            return fail(nullptr, SAP_ERR_UNSUPPORTED, "the plain form needs N(N-1)/2 < 2^32 - 256");
+        if (c->form == SAP_FUSED && 2 * nb * (nb + 1) >= (1ll << 32))
+            return fail(nullptr, SAP_ERR_UNSUPPORTED, "the fused form needs fewer than 2^32 sub-tiles");
+    }
     if (c->rule != SAP_STEP_LITERAL && c->rule != SAP_STEP_NORMALIZED)
         return fail(nullptr, SAP_ERR_INVALID_ARG, "rule must be SAP_STEP_LITERAL or SAP_STEP_NORMALIZED");
     if (!(c->alpha >= 0.0 && c->alpha <= 1.0))
@@ -249,9 +254,6 @@ static sap_status init_plain(sap_ctx *h) {
     h->nchunks = h->pcols / kChunk;
     SAP_TRY(dalloc(h, &h->d_S, es * (size_t)h->n * (size_t)h->pcols));
     SAP_TRY(dalloc(h, &h->d_Pr, es * (size_t)h->n * h->k));
-    SAP_TRY(dalloc(h, &h->d_tmin, sizeof(uint32_t) * h->nchunks));
-    SAP_TRY(dalloc(h, &h->d_tmin2, sizeof(uint32_t) * h->nchunks));
-    SAP_TRY(dalloc(h, &h->d_targ, sizeof(uint32_t) * h->nchunks));
     const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(h->pcols, 256), 65536);
     auto *kept = reinterpret_cast<unsigned long long *>(&h->d_st->kept);
     auto *drop = reinterpret_cast<unsigned long long *>(&h->d_st->dropped);
@@ -289,7 +291,6 @@ static sap_status init_fused(sap_ctx *h) {
     SAP_TRY(dalloc(h, &h->d_tiles, sizeof(int2) * h->ntiles));
     SAP_TRY(dalloc(h, &h->d_invd2, sizeof(float) * (size_t)h->ntiles * kTileElems));
     SAP_TRY(dalloc(h, &h->d_Y, sizeof(float) * (size_t)h->Npad * h->kp));
-    SAP_TRY(dalloc(h, &h->d_tmin, sizeof(uint32_t) * 4 * h->ntiles));
     SAP_HIP(h, hipMemcpyAsync(h->d_tiles, tiles.data(), sizeof(int2) * h->ntiles,
                               hipMemcpyHostToDevice, h->stream));
 
@@ -445,23 +446,21 @@ static SweepArgs<TX> sweep_args(sap_ctx *h, double *tr_min, int64_t *tr_ij, int3
     a.invd2 = h->d_invd2;
     a.tiles = h->d_tiles;
     a.nhalf = 2 * h->ntiles;
-    a.nb = h->nb;
     a.S = static_cast<const TX *>(h->d_S);
     a.pcols = h->pcols;
     a.Pr = static_cast<const TX *>(h->d_Pr);
     a.nchunks = h->nchunks;
     a.n = h->n;
     a.npass = h->pass_grid;
-    a.unit_min = h->d_tmin;
-    a.unit_min2 = h->d_tmin2;
-    a.unit_arg = h->d_targ;
-    a.blk_min = h->d_blk;
     a.close = h->d_close;
     a.cd = h->d_cd;
     a.nclose = h->nclose;
-    a.spart = h->d_part;
+    a.part = h->d_part;
     a.e_abs = h->e_abs;
     a.e_rel = h->e_rel;
+    // item_window coefficients, rounded up to FP32
+    a.wa = std::nextafter((float)((1.0 + h->e_rel) / (1.0 - h->e_rel)), std::numeric_limits<float>::infinity());
+    a.wb = std::nextafter((float)(2.0 * h->e_abs / (1.0 - h->e_rel)), std::numeric_limits<float>::infinity());
     a.X = static_cast<const TX *>(h->X);
     a.ldx = h->ldx;
     a.vx = h->vec_x;
@@ -685,17 +684,10 @@ sap_status sap_init(const sap_config *cfg, const void *X, int64_t ldx, const dou
     if ((s = init_moments(h)) != SAP_OK) return bail(s);
     if ((s = (cfg->form == SAP_PLAIN ? init_plain(h) : init_fused(h))) != SAP_OK) return bail(s);
     if (h->kept == 0) return bail(fail(h, SAP_ERR_NO_PAIRS, "every pair is a duplicate or shorter than min_len"));
-    {
-        // padded to whole uint4 x 256-thread loads of the selection, with keys
-        // that lose every minimum
-        const size_t nblk = (size_t)ceil_div(h->pass_grid, 4 * kPairBlock) * 4 * kPairBlock;
-        if ((s = dalloc(h, &h->d_blk, sizeof(uint32_t) * nblk)) != SAP_OK) return bail(s);
-        e = hipMemsetAsync(h->d_blk, 0xFF, sizeof(uint32_t) * nblk, h->stream);
-        if (e != hipSuccess) return bail(fail(h, SAP_ERR_DEVICE, "hipMemsetAsync: %s", hipGetErrorString(e)));
-    }
-    if ((s = dalloc(h, &h->d_part, sizeof(Partial) * std::max(h->short_grid, 1))) != SAP_OK) return bail(s);
+    if ((s = dalloc(h, &h->d_part, sizeof(Partial) * (size_t)(h->pass_grid + h->short_grid))) != SAP_OK)
+        return bail(s);
     if ((s = load_P(h, P0)) != SAP_OK) return bail(s);
-    h->tail_lds = sizeof(double) * ((size_t)h->k * h->n + 2 * (size_t)h->n + 16);
+    h->tail_lds = sizeof(double) * ((size_t)h->k * h->n + 2 * (size_t)h->n);
     e = hipSuccess;
     SAP_DISPATCH_K(h->k, {
         const void *fns[4] = {reinterpret_cast<const void *>(&k_select<K, float, true>),

@@ -24,14 +24,14 @@ constexpr uint32_t kKeyNone = 0xFFFFFFFFu;  // "no pair": loses every unsigned m
 constexpr float kMaskDropped = -1.0f;  // padding, i >= j, duplicate, d < l
 constexpr float kMaskClose = -2.0f;    // evaluated in FP64 from the close list
 
-// Per-block result of the FP64 rescoring kernel.
+// Per-block result of the pass: the best FP64-rescored pair of the block.
 struct Partial {
-    double r;       // best FP64 r in the block (+inf if none)
-    int32_t i, j;   // its pair
+    double r;         // best FP64 r in the block (+inf if none)
+    int32_t i, j;     // its pair
     int32_t n_rescored;
-    int32_t n_tiles;  // window tiles revisited by the block
+    int32_t n_units;  // work items (half-tiles / chunks) with rescored pairs
     int32_t n_viol;   // rescored pairs whose coarse value broke the error bound
-    int32_t pad;
+    uint32_t kmin;    // smallest coarse key of the block (kKeyNone: none)
 };
 
 // Device-resident record of the last evaluation (read back by the host).

@@ -69,7 +69,8 @@ __device__ __forceinline__ double wave_sum_fast(double v) {
     return pair_sum32(v);
 }
 
-// v[from..NV-1] summed over the wavefront, the reductions interleaved.
+// v[from..NV-1] summed over the wavefront, the reductions interleaved (the
+// same steps as wave_sum_fast, so each sum has the same bits).
 template <int NV>
 __device__ __forceinline__ void wave_sum_many(double (&v)[NV], int from = 0) {
 #pragma unroll
@@ -81,9 +82,9 @@ __device__ __forceinline__ void wave_sum_many(double (&v)[NV], int from = 0) {
 #pragma unroll
     for (int a = 0; a < NV; ++a) if (a >= from) v[a] += dpp_f64<0x140>(v[a]);
 #pragma unroll
-    for (int a = 0; a < NV; ++a) if (a >= from) v[a] += __shfl_xor(v[a], 16, kWave);
+    for (int a = 0; a < NV; ++a) if (a >= from) v[a] = pair_sum16(v[a]);
 #pragma unroll
-    for (int a = 0; a < NV; ++a) if (a >= from) v[a] += __shfl_xor(v[a], 32, kWave);
+    for (int a = 0; a < NV; ++a) if (a >= from) v[a] = pair_sum32(v[a]);
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -305,6 +306,16 @@ __device__ __forceinline__ uint32_t window_key(uint32_t gmin, double e_abs, doub
     return __float_as_uint(f);
 }
 
+// The window of a work item whose smallest key is m, in FP32 and rounded
+// generously upward: T = (sqrt(m) (1 + e_rel) + 2 e_abs) / (1 - e_rel) = sqrt(m) wa + wb,
+// and T^2 (1 + 1e-6) exceeds the exact square by more than the few FP32
+// roundings of sqrt, multiply and add can lose.  A superset only costs
+// rescoring time, never correctness.
+__device__ __forceinline__ uint32_t item_window(uint32_t m, float wa, float wb) {
+    const float t = __builtin_fmaf(__builtin_amdgcn_sqrtf(__uint_as_float(m)), wa, wb);
+    return __float_as_uint(t * t * 1.000001f);
+}
+
 // The proven bound |r~ - r| <= e_abs + e_rel r, checked on every rescored
 // window pair: a violation means the coarse pass is not what the bound
 // describes, and the result is then reported uncertified.
@@ -368,33 +379,6 @@ __device__ __forceinline__ int32_t wave_sum_i32_fast(int32_t v) {
     return b[0] + b[1];
 }
 
-// Block-wide reduction of a per-thread (r, i, j) and counters into *out
-// (written by thread 0).  All 256 threads must call it.
-__device__ void block_reduce_partial(double r, int32_t i, int32_t j, int32_t nres, int32_t ntl,
-                                     int32_t nviol, Partial *out) {
-    __shared__ Partial sb[kPairBlock / kWave];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    wave_min_lex_fast(r, i, j);
-    nres = wave_sum_i32_fast(nres);
-    ntl = wave_sum_i32_fast(ntl);
-    nviol = wave_sum_i32_fast(nviol);
-    if (lane == 0) sb[wv] = Partial{r, i, j, nres, ntl, nviol, 0};
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        Partial b = sb[0];
-        for (int w = 1; w < kPairBlock / kWave; ++w) {
-            if (lex_less(sb[w].r, sb[w].i, sb[w].j, b.r, b.i, b.j)) {
-                b.r = sb[w].r; b.i = sb[w].i; b.j = sb[w].j;
-            }
-            b.n_rescored += sb[w].n_rescored;
-            b.n_tiles += sb[w].n_tiles;
-            b.n_viol += sb[w].n_viol;
-        }
-        *out = b;
-    }
-    __syncthreads();
-}
-
 // Unsigned minimum over the wavefront, in every lane (same exchange pattern
 // as wave_sum_fast; the minimum of a swap's two results is order-free).
 __device__ __forceinline__ uint32_t wave_min_u32_fast(uint32_t v) {
@@ -408,22 +392,33 @@ __device__ __forceinline__ uint32_t wave_min_u32_fast(uint32_t v) {
     return min((uint32_t)b[0], (uint32_t)b[1]);
 }
 
-__device__ __forceinline__ uint32_t block_min_u32(uint32_t v) {
-    __shared__ uint32_t sm[kPairBlock / kWave];
-    v = wave_min_u32_fast(v);
-    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+// Block-wide reduction of a per-thread (r, i, j), counters and coarse minimum
+// into *out (written by thread 0).  All 256 threads must call it.
+__device__ void block_reduce_partial(double r, int32_t i, int32_t j, int32_t nres, int32_t ntl,
+                                     int32_t nviol, uint32_t kmin, Partial *out) {
+    __shared__ Partial sb[kPairBlock / kWave];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    wave_min_lex_fast(r, i, j);
+    nres = wave_sum_i32_fast(nres);
+    ntl = wave_sum_i32_fast(ntl);
+    nviol = wave_sum_i32_fast(nviol);
+    kmin = wave_min_u32_fast(kmin);
+    if (lane == 0) sb[wv] = Partial{r, i, j, nres, ntl, nviol, kmin};
     __syncthreads();
-    uint32_t b = sm[0];
-#pragma unroll
-    for (int w = 1; w < kPairBlock / kWave; ++w) b = min(b, sm[w]);
+    if (threadIdx.x == 0) {
+        Partial b = sb[0];
+        for (int w = 1; w < kPairBlock / kWave; ++w) {
+            if (lex_less(sb[w].r, sb[w].i, sb[w].j, b.r, b.i, b.j)) {
+                b.r = sb[w].r; b.i = sb[w].i; b.j = sb[w].j;
+            }
+            b.n_rescored += sb[w].n_rescored;
+            b.n_units += sb[w].n_units;
+            b.n_viol += sb[w].n_viol;
+            b.kmin = min(b.kmin, sb[w].kmin);
+        }
+        *out = b;
+    }
     __syncthreads();
-    return b;
-}
-
-// Load of a value another block of the same grid wrote (after the acquire
-// in finished_last): a device-scope relaxed atomic load, never a scalar load.
-__device__ __forceinline__ uint32_t ld_u32(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ------------------------------------------------------------------ sweep
@@ -436,7 +431,6 @@ struct SweepArgs {
     const float4 *invd2;
     const int2 *tiles;
     int64_t nhalf;       // 2 x tiles
-    int64_t nb;          // tile rows (the tiles cover the upper triangle of nb x nb)
     // plain pass
     const TX *S;
     int64_t pcols;
@@ -444,18 +438,16 @@ struct SweepArgs {
     int64_t nchunks;
     // both passes
     int n;
-    int npass;           // pass blocks; blocks >= npass are short-pair blocks
-    uint32_t *unit_min;  // per sub-tile (fused) or chunk (plain)
-    uint32_t *unit_min2; // plain: second-smallest key of the chunk
-    uint32_t *unit_arg;  // plain: position (0..255) of the chunk's smallest key
-    uint32_t *blk_min;   // per pass block
+    int npass;           // pass blocks
+    Partial *part;       // npass pass-block results, then one per short-pair block
     // short pairs (fused)
     const int2 *close;    // short pairs (i, j), sorted
     const double *cd;     // their lengths ||x_i - x_j||
     int64_t nclose;
-    Partial *spart;       // per short-pair block
-    // selection
+    // FP64 rescoring and selection
     double e_abs, e_rel;
+    float wa, wb;         // item_window coefficients: (1 + e_rel)/(1 - e_rel), 2 e_abs/(1 - e_rel),
+                          // rounded up
     const TX *X;
     int64_t ldx, N;
     int vx, vp;           // 16-byte loads: X rows aligned; n even (rows of P64t)
@@ -468,40 +460,172 @@ struct SweepArgs {
     int it;
 };
 
+// Element e (runtime) of a lane's key array, as a binary tree of selects
+// over constant indices: no dynamic register indexing, so the array stays in
+// registers.
+template <int LO, int NN, int NK>
+__device__ __forceinline__ uint32_t key_sel(const uint32_t (&key)[NK], int e) {
+    if constexpr (NN == 1) {
+        return key[LO];
+    } else {
+        return e < LO + NN / 2 ? key_sel<LO, NN / 2, NK>(key, e) : key_sel<LO + NN / 2, NN / 2, NK>(key, e);
+    }
+}
+template <int NK>
+__device__ __forceinline__ uint32_t key_at(const uint32_t (&key)[NK], int e) {
+    return key_sel<0, NK, NK>(key, e);
+}
+
+// Candidates of a pass block.  Within a work item (a half-tile or a chunk)
+// whose smallest key is m, every pair with key <= T2(m) is a candidate: the
+// global window is T2(global minimum) <= T2(block minimum) <= T2(m), so every
+// window pair of the iteration is a candidate of its own work item.  Each
+// wavefront appends its candidates (i, j, key) to its LDS list during the
+// pass; after the pass the block keeps those with key <= T2(block minimum)
+// and rescores them in FP64 (wavefront-cooperatively), re-checking each
+// coarse value against the bound.  A full list is first pruned to the
+// wavefront's own running window; if it is still full, the candidate is
+// dropped and the block's result marked uncertified (never silently).
+constexpr int kCandCap = 128;   // candidates per wavefront
+
+struct CandList {
+    int2 *ij;
+    uint32_t *key;
+    int *cnt;       // one LDS word: hands the pruned count to every lane
+    int n;          // wavefront-uniform
+    int lost;       // candidates dropped for lack of space
+};
+
+struct WaveBest {
+    double r;
+    int32_t i, j, nwin, nviol, nunits;
+};
+
+// Append the set bits of the lanes' masks `bits` (slot e of lane l):
+// keyof(l, e) and pair(l, e) give its key and (i, j) from wavefront-uniform
+// arguments.  kmin: the wavefront's running minimum (its window prunes a
+// full list).
+template <typename TX, typename KeyOf, typename PairOf>
+__device__ __forceinline__ void append_cands(const SweepArgs<TX> &a, CandList &cl, uint32_t bits,
+                                             uint32_t kmin, KeyOf keyof, PairOf pair, WaveBest &wb) {
+    const int lane = threadIdx.x & 63;
+    uint64_t lanes = __ballot(bits != 0);
+    if (lanes) ++wb.nunits;
+#pragma unroll 1
+    while (lanes) {
+        const int ln = __builtin_ctzll(lanes);
+        lanes &= lanes - 1;
+        uint32_t lb = __shfl(bits, ln, kWave);
+#pragma unroll 1
+        while (lb) {
+            const int e = __builtin_ctz(lb);
+            lb &= lb - 1;
+            const uint32_t kv = keyof(ln, e);
+            if (cl.n == kCandCap) {
+                // prune to the running window (one lane, in order; rare)
+                const uint32_t T2run = item_window(kmin, a.wa, a.wb);
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) {
+                    int w = 0;
+                    for (int c = 0; c < kCandCap; ++c)
+                        if (cl.key[c] <= T2run) { cl.ij[w] = cl.ij[c]; cl.key[w] = cl.key[c]; ++w; }
+                    *cl.cnt = w;
+                }
+                __builtin_amdgcn_wave_barrier();
+                cl.n = __builtin_amdgcn_readfirstlane(*cl.cnt);
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (cl.n < kCandCap) {
+                int32_t i, j;
+                pair(ln, e, i, j);
+                if (lane == 0) { cl.ij[cl.n] = make_int2(i, j); cl.key[cl.n] = kv; }
+                ++cl.n;
+            } else {
+                ++cl.lost;
+            }
+        }
+    }
+}
+
+// After the pass loop: keep the candidates with key <= T2b, rescore them.
+template <int K, typename TX>
+__device__ __forceinline__ void rescore_cands(const SweepArgs<TX> &a, const CandList &cl,
+                                              uint32_t T2b, WaveBest &wb) {
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+    for (int c = 0; c < cl.n; ++c) {
+        const uint32_t kv = cl.key[c];
+        if (kv > T2b) continue;
+        const int2 ij = cl.ij[c];
+        const double r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, a.P64t, ij.x, ij.y);
+        ++wb.nwin;
+        wb.nviol += bound_broken(r, (double)__uint_as_float(kv), a.e_abs, a.e_rel);
+        if (lex_less(r, ij.x, ij.y, wb.r, wb.i, wb.j)) { wb.r = r; wb.i = ij.x; wb.j = ij.y; }
+    }
+    wb.nviol += cl.lost;   // dropped candidates: the result is not certified
+}
+
+// Block minimum of the wavefronts' coarse minima (uniform per wavefront),
+// then every wavefront rescores its surviving candidates, and the block's
+// result goes to its Partial slot.
+template <int K, typename TX>
+__device__ __forceinline__ void finish_pass_block(const SweepArgs<TX> &a, const CandList &cl,
+                                                  uint32_t kmin, WaveBest &wb, Partial *out) {
+    __shared__ uint32_t s_km[kPairBlock / kWave];
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) s_km[threadIdx.x >> 6] = kmin;
+    __syncthreads();
+    const uint32_t kb = min(min(s_km[0], s_km[1]), min(s_km[2], s_km[3]));
+    if (kb < 0x7f800000u) rescore_cands<K, TX>(a, cl, item_window(kb, a.wa, a.wb), wb);
+    block_reduce_partial(wb.r, wb.i, wb.j, lane == 0 ? wb.nwin : 0, lane == 0 ? wb.nunits : 0,
+                         lane == 0 ? wb.nviol : 0, kmin, out);
+}
+
 // Fused pass block pb.  Wavefront w = 4 pb + slot takes half-tiles
 // h = w, w + nw, ... (h = 2 t + half: rows 64 bi + 32 half .. +31 against the
-// 64 columns of tile t = (bi, bj)).  Before scoring a half-tile it issues
-// every load of the next one (8 weight float4 per lane, the lane's y_j, its
-// share of the 32 y_i rows), so memory latency overlaps the arithmetic; the
-// y_i rows go through the wavefront's own LDS slice (read back as
-// broadcasts; no other wavefront touches it, so no block barrier).
-// Per pair: K subtractions, K FMAs, one multiply, one unsigned min.
+// 64 columns of tile t = (bi, bj)).  Every load of a half-tile (8 weight
+// float4 per lane, the lane's y_j, its share of the 32 y_i rows) is issued
+// at once, before any is used; the y_i rows go through the wavefront's own
+// LDS slice (read back as broadcasts; no other wavefront touches it, so no
+// block barrier).
+// Per pair: K subtractions, K FMAs, one multiply, one unsigned min, one
+// compare against the half-tile's window.  Candidates are rescored after the
+// loop (finish_pass_block).
 template <int K, typename TX>
-__device__ uint32_t fused_pass_block(const SweepArgs<TX> &a, int pb) {
+__device__ void fused_pass_block(const SweepArgs<TX> &a, int pb) {
     __shared__ float4 s_y[kPairBlock / kWave][32 * kMaxK / 4];
+    __shared__ int2 s_cij[kPairBlock / kWave][kCandCap];
+    __shared__ uint32_t s_ckey[kPairBlock / kWave][kCandCap];
+    __shared__ int s_ccnt[kPairBlock / kWave];
+    // the half-tile's keys: lane l's 32 at l*36 (16-byte rows, padded)
+    __shared__ uint4 s_kb[kPairBlock / kWave][kWave * 9];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nw = (int64_t)a.npass * (kPairBlock / kWave);
     const int kp = a.kp;
+    uint4 *kb4 = s_kb[wv];
     float4 *yl = s_y[wv];
     const int nf4 = 8 * kp;                  // float4 count of 32 rows of Y (<= 128)
-    uint32_t best = kKeyNone;
+    WaveBest wb{__builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0};
+    CandList cl{s_cij[wv], s_ckey[wv], &s_ccnt[wv], 0, 0};
+    uint32_t kmin = kKeyNone, T2run = 0;   // running minimum and its window
     int64_t h = (int64_t)pb * (kPairBlock / kWave) + wv;
-    // loads of half-tile h: weights, y_j, and two float4 of the y_i rows per lane
+    // loads of half-tile h: weights, tile, y_j, two float4 of the y_i rows per lane
     float4 w[8], yr0, yr1;
     float yj[K];
-    auto fetch = [&](int64_t hh) {
+    int2 bt;
+    auto fetch = [&](int64_t hh) __attribute__((always_inline)) {
         const int64_t t = hh >> 1;
         const int half = (int)(hh & 1);
         const float4 *tp = a.invd2 + t * (kTileElems / 4) + half * 512 + lane;
 #pragma unroll
         for (int g = 0; g < 8; ++g) w[g] = tp[g * 64];
-        const int2 b = a.tiles[t];
+        bt = a.tiles[t];
         const float4 *ysrc =
-            reinterpret_cast<const float4 *>(a.Y + ((int64_t)b.x * kTile + 32 * half) * kp);
+            reinterpret_cast<const float4 *>(a.Y + ((int64_t)bt.x * kTile + 32 * half) * kp);
         yr0 = ysrc[lane < nf4 ? lane : 0];
         yr1 = ysrc[lane + 64 < nf4 ? lane + 64 : 0];
-        load_yj<K>(a.Y, kp, (int64_t)b.y * kTile + lane, yj);
+        load_yj<K>(a.Y, kp, (int64_t)bt.y * kTile + lane, yj);
     };
     if (h < a.nhalf) fetch(h);
     for (; h < a.nhalf; h += nw) {
@@ -511,73 +635,95 @@ __device__ uint32_t fused_pass_block(const SweepArgs<TX> &a, int pb) {
         float yc[K];
 #pragma unroll
         for (int c = 0; c < K; ++c) yc[c] = yj[c];
+        const int32_t row0 = bt.x * kTile + 32 * (int32_t)(h & 1), col0 = bt.y * kTile;
         __builtin_amdgcn_wave_barrier();
         if (lane < nf4) yl[lane] = yr0;
         if (lane + 64 < nf4) yl[lane + 64] = yr1;
         __builtin_amdgcn_wave_barrier();
-        if (h + nw < a.nhalf) fetch(h + nw);     // next half-tile's loads in flight
         const float *yi0 = reinterpret_cast<const float *>(yl);
-        uint32_t m0 = kKeyNone, m1 = kKeyNone;
+        // the lane's 32 keys go to its row of the LDS key block as they are
+        // produced (nothing stays live across the window computation)
+        uint32_t lmin = kKeyNone;
 #pragma unroll
         for (int g = 0; g < 8; ++g) {
             const float *yi = yi0 + 4 * g * kp;
-            uint32_t m = min(__float_as_uint(pair_r2<K>(yi, yc, wc[g].x)),
-                             __float_as_uint(pair_r2<K>(yi + kp, yc, wc[g].y)));
-            m = min(m, __float_as_uint(pair_r2<K>(yi + 2 * kp, yc, wc[g].z)));
-            m = min(m, __float_as_uint(pair_r2<K>(yi + 3 * kp, yc, wc[g].w)));
-            if (g < 4) m0 = min(m0, m); else m1 = min(m1, m);
+            const uint32_t k0 = __float_as_uint(pair_r2<K>(yi, yc, wc[g].x));
+            const uint32_t k1 = __float_as_uint(pair_r2<K>(yi + kp, yc, wc[g].y));
+            const uint32_t k2 = __float_as_uint(pair_r2<K>(yi + 2 * kp, yc, wc[g].z));
+            const uint32_t k3 = __float_as_uint(pair_r2<K>(yi + 3 * kp, yc, wc[g].w));
+            kb4[lane * 9 + g] = make_uint4(k0, k1, k2, k3);
+            lmin = min(lmin, min(min(k0, k1), min(k2, k3)));
         }
-        m0 = wave_min_u32_fast(m0);
-        m1 = wave_min_u32_fast(m1);
-        if (lane == 0) {
-            a.unit_min[2 * h] = m0;
-            a.unit_min[2 * h + 1] = m1;
+        const uint32_t m = wave_min_u32_fast(lmin);
+        if (m < kmin) { kmin = m; T2run = item_window(m, a.wa, a.wb); }
+        // the block window is at most the window of the wavefront's running
+        // minimum: a half-tile whose minimum lies outside it has no candidate
+        if (m <= T2run) {
+            const uint32_t T2 = T2run;
+            uint32_t bits = 0;
+            __builtin_amdgcn_wave_barrier();
+            if (lmin <= T2) {
+#pragma unroll
+                for (int g = 0; g < 8; ++g) {
+                    const uint4 q = kb4[lane * 9 + g];
+                    bits |= ((q.x <= T2 ? 1u : 0u) | (q.y <= T2 ? 2u : 0u) | (q.z <= T2 ? 4u : 0u) |
+                             (q.w <= T2 ? 8u : 0u)) << (4 * g);
+                }
+            }
+            const uint32_t *kb = reinterpret_cast<const uint32_t *>(kb4);
+            append_cands(a, cl, bits, kmin,
+                         [=](int ln, int e) __attribute__((always_inline)) { return kb[ln * 36 + e]; },
+                         [=](int ln, int e, int32_t &i, int32_t &j) __attribute__((always_inline)) {
+                             i = row0 + e;
+                             j = col0 + ln;
+                         },
+                         wb);
         }
-        best = min(best, min(m0, m1));
         __builtin_amdgcn_wave_barrier();
+        if (h + nw < a.nhalf) fetch(h + nw);     // the next half-tile's loads
     }
-    return block_min_u32(best);
+    finish_pass_block<K, TX>(a, cl, kmin, wb, a.part + pb);
 }
 
-// Plain pass block: one wavefront per 256-pair chunk (grid-stride).
+// Plain pass block: one wavefront per 256-pair chunk (grid-stride), the
+// same candidate scheme per chunk.
 template <int K, typename TX>
-__device__ uint32_t plain_pass_block(const SweepArgs<TX> &a, int pb) {
+__device__ void plain_pass_block(const SweepArgs<TX> &a, int pb) {
+    __shared__ int2 s_cij[kPairBlock / kWave][kCandCap];
+    __shared__ uint32_t s_ckey[kPairBlock / kWave][kCandCap];
+    __shared__ int s_ccnt[kPairBlock / kWave];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t wid = (int64_t)pb * (kPairBlock / kWave) + wv;
     const int64_t nw = (int64_t)a.npass * (kPairBlock / kWave);
-    uint32_t best = kKeyNone;
+    WaveBest wb{__builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0};
+    CandList cl{s_cij[wv], s_ckey[wv], &s_ccnt[wv], 0, 0};
+    uint32_t kmin = kKeyNone, T2run = 0;   // running minimum and its window
     for (int64_t ch = wid; ch < a.nchunks; ch += nw) {
         TX r2[4];
         plain_r2<K, TX>(a.S, a.pcols, a.n, a.Pr, ch * kChunk + lane * 4, r2);
-        uint32_t kk[4];
+        uint32_t key[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) kk[e] = key_of<TX>(r2[e]);
-        // the chunk's smallest and second-smallest keys: the selection
-        // rescores a chunk's single window pair directly, without a rescan,
-        // when the second-smallest key lies outside the window
-        uint32_t m1 = min(kk[0], kk[1]), m2 = max(kk[0], kk[1]);
+        for (int e = 0; e < 4; ++e) key[e] = key_of<TX>(r2[e]);
+        const uint32_t m = wave_min_u32_fast(min(min(key[0], key[1]), min(key[2], key[3])));
+        if (m < kmin) { kmin = m; T2run = item_window(m, a.wa, a.wb); }
+        if (m <= T2run) {
+            const uint32_t T2 = T2run;
+            uint32_t bits = 0;
 #pragma unroll
-        for (int e = 2; e < 4; ++e) { m2 = min(m2, max(m1, kk[e])); m1 = min(m1, kk[e]); }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const uint32_t x1 = __shfl_xor(m1, o, kWave), x2 = __shfl_xor(m2, o, kWave);
-            m2 = min(min(m2, x2), max(m1, x1));
-            m1 = min(m1, x1);
+            for (int e = 0; e < 4; ++e) bits |= (key[e] <= T2 ? 1u : 0u) << e;
+            append_cands(a, cl, bits, kmin,
+                         [&](int ln, int e) { return (uint32_t)__shfl((int)key_at<4>(key, e), ln, kWave); },
+                         [=](int ln, int e, int32_t &i, int32_t &j) __attribute__((always_inline)) {
+                             int64_t ii, jj;
+                             decode_pair(ch * kChunk + ln * 4 + e, a.N, ii, jj);
+                             i = (int32_t)ii;
+                             j = (int32_t)jj;
+                         },
+                         wb);
         }
-        // position of the first pair holding the smallest key
-        const int ef = kk[0] == m1 ? 0 : kk[1] == m1 ? 1 : kk[2] == m1 ? 2 : kk[3] == m1 ? 3 : 4;
-        const uint64_t bal = __ballot(ef < 4);
-        const int fl = bal ? __builtin_ctzll(bal) : 0;
-        const int arg = fl * 4 + __shfl(ef, fl, kWave);
-        if (lane == 0) {
-            a.unit_min[ch] = m1;
-            a.unit_min2[ch] = m2;
-            a.unit_arg[ch] = (uint32_t)arg;
-        }
-        best = min(best, m1);
     }
-    return block_min_u32(best);
+    finish_pass_block<K, TX>(a, cl, kmin, wb, a.part + pb);
 }
 
 // c = P^T (x_i - x_j) for 16 short pairs in FP64 on the matrix cores, tiled
@@ -656,227 +802,43 @@ __device__ void short_block(const SweepArgs<TX> &a, int sb, int nshort) {
             }
         }
     }
-    block_reduce_partial(best, bi, bj, cnt, 0, 0, a.spart + sb);
+    block_reduce_partial(best, bi, bj, cnt, 0, 0, kKeyNone, a.part + a.npass + sb);
 }
 
-// Revisit one 16 x 64 sub-tile u (wavefront): every pair whose coarse value is
-// inside the window is rescored in FP64 and its bound re-checked.
-// Tile t of the upper triangle of nb x nb tiles, numbered row by row:
-// t = bi nb - bi (bi - 1) / 2 + (bj - bi).
-__device__ __forceinline__ int2 tile_coords(int64_t t, int64_t nb) {
-    const double c = 2.0 * (double)nb + 1.0;
-    const double disc = c * c - 8.0 * (double)t;
-    int64_t bi = (int64_t)floor((c - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
-    if (bi < 0) bi = 0;
-    if (bi > nb - 1) bi = nb - 1;
-    while (bi > 0 && bi * nb - bi * (bi - 1) / 2 > t) --bi;
-    while (bi < nb - 1 && (bi + 1) * nb - (bi + 1) * bi / 2 <= t) ++bi;
-    const int64_t bj = t - (bi * nb - bi * (bi - 1) / 2) + bi;
-    return make_int2((int)bi, (int)bj);
-}
-
-template <int K, typename TX>
-__device__ void revisit_subtile(const SweepArgs<TX> &a, const double *Pl, int64_t u, uint32_t T2,
-                                double &best, int32_t &bi, int32_t &bj, int32_t &nwin,
-                                int32_t &nviol) {
-    __shared__ float4 s_ry[kPairBlock / kWave][16 * kMaxK / 4];
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int2 b = tile_coords(u >> 2, a.nb);
-    const int32_t row0 = b.x * kTile + (int32_t)(u & 3) * 16;
-    // every load of the sub-tile issued together; its 16 y_i rows go to this
-    // wavefront's LDS slice (read back as broadcasts)
-    const float4 *tp = a.invd2 + (u >> 2) * (kTileElems / 4) + (u & 3) * 256 + lane;
-    const float4 w0 = tp[0], w1 = tp[64], w2 = tp[128], w3 = tp[192];
-    float yj[K];
-    load_yj<K>(a.Y, a.kp, (int64_t)b.y * kTile + lane, yj);
-    const float4 *ysrc = reinterpret_cast<const float4 *>(a.Y + (int64_t)row0 * a.kp);
-    __builtin_amdgcn_wave_barrier();
-    if (lane < 4 * a.kp) s_ry[wv][lane] = ysrc[lane];
-    __builtin_amdgcn_wave_barrier();
-    const float *yi0 = reinterpret_cast<const float *>(s_ry[wv]);
-    // loops kept rolled: one copy of the FP64 evaluation below
-#pragma unroll 1
-    for (int g = 0; g < 4; ++g) {
-        const float4 w4 = g == 0 ? w0 : g == 1 ? w1 : g == 2 ? w2 : w3;
-#pragma unroll 1
-        for (int rr = 0; rr < 4; ++rr) {
-            const float wr = rr == 0 ? w4.x : rr == 1 ? w4.y : rr == 2 ? w4.z : w4.w;
-            const float r2 = pair_r2<K>(yi0 + (int64_t)(4 * g + rr) * a.kp, yj, wr);
-            uint64_t cm = __ballot(__float_as_uint(r2) <= T2);
-            while (cm) {
-                const int ln = __builtin_ctzll(cm);
-                cm &= cm - 1;
-                const int32_t i = row0 + 4 * g + rr;
-                const int32_t j = b.y * kTile + ln;
-                const double r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, Pl, i, j);
-                const float r2c = __shfl(r2, ln, kWave);
-                ++nwin;
-                nviol += bound_broken(r, (double)r2c, a.e_abs, a.e_rel);
-                if (lex_less(r, i, j, best, bi, bj)) { best = r; bi = i; bj = j; }
-            }
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
-}
-
-// Rescan one 256-pair chunk of the plain form (wavefront): used only when the
-// chunk may hold more than one window pair.
-template <int K, typename TX>
-__device__ void revisit_chunk(const SweepArgs<TX> &a, const double *Pl, int64_t ch, uint32_t T2,
-                              double &best, int32_t &bi, int32_t &bj, int32_t &nwin,
-                              int32_t &nviol) {
-    const int lane = threadIdx.x & 63;
-    TX r2[4];
-    plain_r2<K, TX>(a.S, a.pcols, a.n, a.Pr, ch * kChunk + lane * 4, r2);
-#pragma unroll 1
-    for (int e = 0; e < 4; ++e) {   // rolled: one copy of the FP64 evaluation
-        const TX re = e == 0 ? r2[0] : e == 1 ? r2[1] : e == 2 ? r2[2] : r2[3];
-        uint64_t cm = __ballot(key_of<TX>(re) <= T2);
-        while (cm) {
-            const int ln = __builtin_ctzll(cm);
-            cm &= cm - 1;
-            int64_t i, j;
-            decode_pair(ch * kChunk + ln * 4 + e, a.N, i, j);
-            const double r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, Pl, i, j);
-            const TX r2c = __shfl(re, ln, kWave);
-            ++nwin;
-            nviol += bound_broken(r, (double)r2c, a.e_abs, a.e_rel);
-            if (lex_less(r, (int32_t)i, (int32_t)j, best, bi, bj)) {
-                best = r; bi = (int32_t)i; bj = (int32_t)j;
-            }
-        }
-    }
-}
-
-// Selection (one block, after the pass): coarse minimum, window, FP64
-// rescoring, record.  Wavefront w of the block revisits the units that
-// wavefront slot w of each pass block produced, restricted to the pass
-// blocks whose minimum lies inside the window.  Returns the winning pair in
-// every thread (i < 0 if there is none).  Every dependent global round trip
-// costs about a microsecond here, so each phase issues all of its loads
-// before it uses any.
-constexpr int kFlagCap = 512;        // flagged pass blocks listed in LDS (else a full scan)
-constexpr int kBlkVec = 8;           // uint4 loads of block minima per thread: npass <= 8192
-constexpr int kShortPerThread = 4;   // short-pair blocks per thread: <= 1024
-
+// Selection (one block, after the pass): the lexicographic minimum of every
+// pass block's and short-pair block's FP64 result, the record, and the
+// coarse minimum with its window (reported).  Four partials per thread are
+// loaded per step, all before any is used.  Returns the winning pair in
+// every thread (i < 0 if there is none).
 template <int K, typename TX, bool FUSED>
-__device__ int2 select_min(const SweepArgs<TX> &a, int nshort, const double *Pl) {
-    __shared__ int s_flag[kFlagCap];
-    __shared__ int s_nflag;
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // per-block coarse minima (the array is padded with kKeyNone to a
-    // multiple of 4 x 256 entries) and the short-pair partials (FP64)
-    uint4 bm[kBlkVec];
-    const int nvec = (a.npass + 4 * kPairBlock - 1) / (4 * kPairBlock);
-#pragma unroll
-    for (int m = 0; m < kBlkVec; ++m)
-        bm[m] = m < nvec ? reinterpret_cast<const uint4 *>(a.blk_min)[threadIdx.x + m * kPairBlock]
-                         : make_uint4(kKeyNone, kKeyNone, kKeyNone, kKeyNone);
+__device__ int2 select_min(const SweepArgs<TX> &a, int nparts) {
     double best = __builtin_huge_val();
-    int32_t bi = 0x7fffffff, bj = 0x7fffffff, nres_short = 0;
+    int32_t bi = 0x7fffffff, bj = 0x7fffffff, nres = 0, nunits = 0, nviol = 0;
+    uint32_t kmin = kKeyNone;
+#pragma unroll 1
+    for (int base = 0; base < nparts; base += 4 * kPairBlock) {
+        Partial p[4];
 #pragma unroll
-    for (int m = 0; m < kShortPerThread; ++m) {
-        const int sb = (int)threadIdx.x + m * kPairBlock;
-        if (sb < nshort) {
-            const Partial p = a.spart[sb];
-            if (lex_less(p.r, p.i, p.j, best, bi, bj)) { best = p.r; bi = p.i; bj = p.j; }
-            nres_short += p.n_rescored;
+        for (int u = 0; u < 4; ++u) {
+            const int ix = base + u * kPairBlock + (int)threadIdx.x;
+            p[u] = ix < nparts ? a.part[ix]
+                               : Partial{__builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0, kKeyNone};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (lex_less(p[u].r, p[u].i, p[u].j, best, bi, bj)) { best = p[u].r; bi = p[u].i; bj = p[u].j; }
+            nres += p[u].n_rescored;
+            nunits += p[u].n_units;
+            nviol += p[u].n_viol;
+            kmin = min(kmin, p[u].kmin);
         }
     }
-    uint32_t g = kKeyNone;
-#pragma unroll
-    for (int m = 0; m < kBlkVec; ++m) g = min(g, min(min(bm[m].x, bm[m].y), min(bm[m].z, bm[m].w)));
-    if (threadIdx.x == 0) s_nflag = 0;
-    g = block_min_u32(g);
-    double coarse, tr;
-    const uint32_t T2 = window_key(g, a.e_abs, a.e_rel, &coarse, &tr);
-    // pass blocks whose minimum lies inside the window: a bit mask of the
-    // thread's 4 kBlkVec entries, then its set bits
-    if (coarse >= 0.0) {
-        uint32_t fm = 0;
-#pragma unroll
-        for (int m = 0; m < kBlkVec; ++m)
-            fm |= (bm[m].x <= T2 ? 1u : 0u) << (4 * m) | (bm[m].y <= T2 ? 2u : 0u) << (4 * m) |
-                  (bm[m].z <= T2 ? 4u : 0u) << (4 * m) | (bm[m].w <= T2 ? 8u : 0u) << (4 * m);
-#pragma unroll 1
-        while (fm) {
-            const int bit = __builtin_ctz(fm);
-            fm &= fm - 1;
-            const int at = atomicAdd(&s_nflag, 1);
-            if (at < kFlagCap) s_flag[at] = 4 * ((int)threadIdx.x + (bit >> 2) * kPairBlock) + (bit & 3);
-        }
-    }
-    __syncthreads();
-    const int nflag = s_nflag;
-    int32_t nres = 0, ntl = 0, nviol = 0, nwin = 0;
-    if (coarse >= 0.0) {
-        const int64_t nw = (int64_t)a.npass * (kPairBlock / kWave);
-        const int64_t nunits_w = FUSED ? a.nhalf : a.nchunks;   // work items of the pass
-        // the list order depends on LDS atomics, but the set does not, and
-        // the result is a lexicographic minimum over the set
-        const bool listed = nflag <= kFlagCap;
-        const int nscan = listed ? nflag : a.npass;
-#pragma unroll 1
-        for (int f = 0; f < nscan; ++f) {
-            const int b = listed ? s_flag[f] : f;
-            if (!listed && a.blk_min[b] > T2) continue;
-            // the work items of wavefront slot wv of block b, 64 at a time
-#pragma unroll 1
-            for (int64_t h0 = (int64_t)b * (kPairBlock / kWave) + wv; h0 < nunits_w; h0 += kWave * nw) {
-                const int64_t hl = h0 + lane * nw;
-                uint32_t u0 = kKeyNone, u1 = kKeyNone, ag = 0;
-                if (hl < nunits_w) {
-                    if constexpr (FUSED) {
-                        u0 = a.unit_min[2 * hl];
-                        u1 = a.unit_min[2 * hl + 1];
-                    } else {
-                        u0 = a.unit_min[hl];
-                        u1 = a.unit_min2[hl];
-                        ag = a.unit_arg[hl];
-                    }
-                }
-                uint64_t hits = __ballot((FUSED ? min(u0, u1) : u0) <= T2);
-                while (hits) {
-                    const int ln = __builtin_ctzll(hits);
-                    hits &= hits - 1;
-                    const int64_t h = h0 + (int64_t)ln * nw;
-                    const uint32_t v0 = __shfl(u0, ln, kWave), v1 = __shfl(u1, ln, kWave);
-                    if constexpr (FUSED) {
-#pragma unroll 1
-                        for (int x = 0; x < 2; ++x) {   // one call site
-                            if ((x == 0 ? v0 : v1) <= T2) {
-                                ++ntl;
-                                revisit_subtile<K, TX>(a, Pl, 2 * h + x, T2, best, bi, bj, nwin, nviol);
-                            }
-                        }
-                    } else {
-                        ++ntl;
-                        if (v1 > T2) {
-                            // the chunk's only window pair: rescore it directly
-                            int64_t i, j;
-                            decode_pair(h * kChunk + __shfl(ag, ln, kWave), a.N, i, j);
-                            const double r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, Pl, i, j);
-                            ++nwin;
-                            nviol += bound_broken(r, (double)__uint_as_float(v0), a.e_abs, a.e_rel);
-                            if (lex_less(r, (int32_t)i, (int32_t)j, best, bi, bj)) {
-                                best = r; bi = (int32_t)i; bj = (int32_t)j;
-                            }
-                        } else {
-                            revisit_chunk<K, TX>(a, Pl, h, T2, best, bi, bj, nwin, nviol);
-                        }
-                    }
-                }
-            }
-        }
-    }
-    if (lane != 0) { nwin = 0; ntl = 0; nviol = 0; }
-    nres = nwin + nres_short;
     __shared__ Partial s_fin;
-    block_reduce_partial(best, bi, bj, nres, ntl, nviol, &s_fin);
+    block_reduce_partial(best, bi, bj, nres, nunits, nviol, kmin, &s_fin);
     if (threadIdx.x == 0) {
         const Partial f = s_fin;
+        double coarse, tr;
+        (void)window_key(f.kmin, a.e_abs, a.e_rel, &coarse, &tr);
         const bool found = f.r < __builtin_huge_val();
         const int cert = (found && f.n_viol == 0) ? 1 : 0;
         DevResult *res = a.res;
@@ -888,7 +850,7 @@ __device__ int2 select_min(const SweepArgs<TX> &a, int nshort, const double *Pl)
         res->window = coarse >= 0.0 ? tr - coarse : 0.0;
         res->certified = cert;
         res->n_rescored = f.n_rescored;
-        res->n_tiles = f.n_tiles;
+        res->n_tiles = f.n_units;
         res->t = -1;
         if (a.tr_min) a.tr_min[a.it] = f.r;
         if (a.tr_ij) {
@@ -896,7 +858,7 @@ __device__ int2 select_min(const SweepArgs<TX> &a, int nshort, const double *Pl)
             a.tr_ij[2 * a.it + 1] = found ? f.j : -1;
         }
         if (a.tr_cert) a.tr_cert[a.it] = cert;
-        *a.gmin_out = g;
+        *a.gmin_out = f.kmin;
     }
     __syncthreads();
     const Partial f = s_fin;
@@ -908,8 +870,9 @@ __device__ int2 select_min(const SweepArgs<TX> &a, int nshort, const double *Pl)
 // coarse blocks), the other npass blocks score every pair coarsely.  Every
 // block writes its own result slot; the kernel boundary is the grid-wide
 // barrier before selection.
+// (at least three wavefronts per SIMD: the register budget is 168)
 template <int K, typename TX, bool FUSED>
-__global__ __launch_bounds__(kPairBlock) void k_pass(SweepArgs<TX> a, int nshort) {
+__global__ __launch_bounds__(kPairBlock, 3) void k_pass(SweepArgs<TX> a, int nshort) {
     if constexpr (FUSED) {
         if ((int)blockIdx.x < nshort) {
             short_block<K, TX>(a, (int)blockIdx.x, nshort);
@@ -917,10 +880,8 @@ __global__ __launch_bounds__(kPairBlock) void k_pass(SweepArgs<TX> a, int nshort
         }
     }
     const int pb = (int)blockIdx.x - (FUSED ? nshort : 0);
-    uint32_t best;
-    if constexpr (FUSED) best = fused_pass_block<K, TX>(a, pb);
-    else best = plain_pass_block<K, TX>(a, pb);
-    if (threadIdx.x == 0) a.blk_min[pb] = best;
+    if constexpr (FUSED) fused_pass_block<K, TX>(a, pb);
+    else plain_pass_block<K, TX>(a, pb);
 }
 
 // Fused form, before the pass: Y = (X - mu) P.
@@ -938,13 +899,16 @@ __global__ __launch_bounds__(kPairBlock) void k_prep(SweepArgs<TX> a, const doub
 //   else:       v = P c; modified Gram-Schmidt on (v, p_1..p_k without p_t);
 //               u = unit((1-a) v + a (s - v))   [rule 1: unit vectors of v, s-v]
 //               P' = [u, q_2, .., q_k]
-// The vectors live in LDS (A: K x n, then s, v, c); lane l owns components
+// The vectors live in LDS (A: K x n, then s, v); lane l owns components
 // l, l+64, ...; every inner product is a wavefront sum.  Modified
 // Gram-Schmidt runs right-looking: once q_m is final, every later vector
 // loses its component along q_m (per vector, the same sequence of
-// subtractions as the column-by-column form).  The loops are deliberately
-// not unrolled: this code runs once per launch, and straight-line code is
-// bound by instruction fetch.
+// subtractions as the column-by-column form).  The independent inner
+// products of one step (the K entries of c; the projections of all later
+// vectors on q_m) are reduced together, so a step waits on two reductions
+// (|a_m| and the batch), not on one per vector.  The loop over m is not
+// unrolled: this code runs once per launch, and straight-line code is bound
+// by instruction fetch.
 template <int K, typename TX>
 __device__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
                              double *__restrict__ P64t, double *__restrict__ P64r,
@@ -954,7 +918,6 @@ __device__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
     double *A = sm;                       // K x n: P (loaded by the caller), then MGS vectors
     double *s = sm + (size_t)K * n;       // unit secant, later u
     double *v = s + n;                    // P P^T s
-    double *c = v + n;                    // P^T s (16 slots)
     double d2 = 0.0;
     for (int l = lane; l < n; l += kWave) {
         const double dl = (double)X[i * ldx + l] - (double)X[j * ldx + l];
@@ -962,18 +925,22 @@ __device__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
         d2 = __builtin_fma(dl, dl, d2);
     }
     const double d = sqrt(wave_sum_fast(d2));
-    for (int l = lane; l < n; l += kWave) s[l] = s[l] / d;
     // c = P^T s, t = first argmax |c_t| (every lane holds the same sums)
+    double c[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) c[q] = 0.0;
+    for (int l = lane; l < n; l += kWave) {
+        const double sl = s[l] / d;
+        s[l] = sl;
+#pragma unroll
+        for (int q = 0; q < K; ++q) c[q] = __builtin_fma(A[(size_t)q * n + l], sl, c[q]);
+    }
+    wave_sum_many<K>(c);
     int t = 0;
     double cmax = -1.0;
-#pragma unroll 1
-    for (int q = 0; q < K; ++q) {
-        double acc = 0.0;
-        for (int l = lane; l < n; l += kWave) acc = __builtin_fma(A[(size_t)q * n + l], s[l], acc);
-        acc = wave_sum_fast(acc);
-        if (lane == 0) c[q] = acc;
-        if (fabs(acc) > cmax) { cmax = fabs(acc); t = q; }
-    }
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+        if (fabs(c[q]) > cmax) { cmax = fabs(c[q]); t = q; }
     if (lane == 0) res->t = t;
 
     if (cmax == 0.0) {
@@ -982,7 +949,7 @@ __device__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
         // v = P c; MGS input order (v, p_1..p_{t-1}, p_{t+1}..p_k), in place
         for (int l = lane; l < n; l += kWave) {
             double acc = 0.0;
-#pragma unroll 1
+#pragma unroll
             for (int q = 0; q < K; ++q) acc = __builtin_fma(A[(size_t)q * n + l], c[q], acc);
             v[l] = acc;
             for (int m = t; m > 0; --m) A[(size_t)m * n + l] = A[(size_t)(m - 1) * n + l];
@@ -996,14 +963,22 @@ __device__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
             for (int l = lane; l < n; l += kWave) nn = __builtin_fma(am[l], am[l], nn);
             const double nrm = sqrt(wave_sum_fast(nn));
             if (m == 0) vnorm = nrm;
-            for (int l = lane; l < n; l += kWave) am[l] = am[l] / nrm;
-#pragma unroll 1
-            for (int jv = m + 1; jv < K; ++jv) {
-                double *aj = A + (size_t)jv * n;
-                double dot = 0.0;
-                for (int l = lane; l < n; l += kWave) dot = __builtin_fma(am[l], aj[l], dot);
-                dot = wave_sum_fast(dot);
-                for (int l = lane; l < n; l += kWave) aj[l] = aj[l] - dot * am[l];
+            double dots[K];
+#pragma unroll
+            for (int jv = 0; jv < K; ++jv) dots[jv] = 0.0;
+            for (int l = lane; l < n; l += kWave) {
+                const double q = am[l] / nrm;
+                am[l] = q;
+#pragma unroll
+                for (int jv = 0; jv < K; ++jv)
+                    if (jv > m) dots[jv] = __builtin_fma(q, A[(size_t)jv * n + l], dots[jv]);
+            }
+            wave_sum_many<K>(dots, m + 1);
+            for (int l = lane; l < n; l += kWave) {
+                const double q = am[l];
+#pragma unroll
+                for (int jv = 0; jv < K; ++jv)
+                    if (jv > m) A[(size_t)jv * n + l] = A[(size_t)jv * n + l] - dots[jv] * q;
             }
         }
         // the alpha shift toward the worst secant
@@ -1031,7 +1006,7 @@ __device__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
     }
     // write back: master (K x n), row-major FP64 copy, and the plain pass's copy
     for (int l = lane; l < n; l += kWave) {
-#pragma unroll 1
+#pragma unroll
         for (int q = 0; q < K; ++q) {
             const double pv = A[(size_t)q * n + l];
             P64t[(int64_t)q * n + l] = pv;
@@ -1169,7 +1144,7 @@ __device__ __forceinline__ void apply_update_reg(const TX *__restrict__ X, int64
 
 // Selection, record and (do_step) update, in one block.  Dynamic LDS holds
 // P (read by the rescoring, then the update's working copy) and the update's
-// vectors: (K + 2) n + 16 doubles.
+// vectors: (K + 2) n doubles.
 template <int K, typename TX, bool FUSED>
 __global__ __launch_bounds__(kPairBlock) void k_select(SweepArgs<TX> a, int nshort,
                                                        double *__restrict__ P64t,
@@ -1177,10 +1152,10 @@ __global__ __launch_bounds__(kPairBlock) void k_select(SweepArgs<TX> a, int nsho
                                                        void *__restrict__ Pr, int pr_kind,
                                                        double alpha, int rule, int do_step) {
     extern __shared__ double sm_dyn[];
-    // P into LDS now, so that its loads overlap the first phase (the block
-    // barriers inside select_min order these writes before any read)
+    // P into LDS now, so that its loads overlap the selection (the block
+    // barriers inside select_min order these writes before the update)
     for (int e = threadIdx.x; e < K * a.n; e += kPairBlock) sm_dyn[e] = a.P64t[e];
-    const int2 ij = select_min<K, TX, FUSED>(a, nshort, sm_dyn);
+    const int2 ij = select_min<K, TX, FUSED>(a, a.npass + nshort);
     if (do_step && ij.x >= 0 && threadIdx.x < kWave) {
         // registers when every vector fits one 64-lane slice and K is
         // small, LDS otherwise
