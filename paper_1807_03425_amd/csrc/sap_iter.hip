@@ -807,8 +807,9 @@ __device__ void short_block(const SweepArgs<TX> &a, int sb, int nshort) {
 
 // Selection (one block, after the pass): the lexicographic minimum of every
 // pass block's and short-pair block's FP64 result, the record, and the
-// coarse minimum with its window (reported).  Four partials per thread are
-// loaded per step, all before any is used.  Returns the winning pair in
+// coarse minimum with its window (reported).  Eight partials per thread are
+// loaded per step, all before any is used (each step is a round trip to
+// memory written by other dies' caches).  Returns the winning pair in
 // every thread (i < 0 if there is none).
 template <int K, typename TX, bool FUSED>
 __device__ int2 select_min(const SweepArgs<TX> &a, int nparts) {
@@ -816,16 +817,18 @@ __device__ int2 select_min(const SweepArgs<TX> &a, int nparts) {
     int32_t bi = 0x7fffffff, bj = 0x7fffffff, nres = 0, nunits = 0, nviol = 0;
     uint32_t kmin = kKeyNone;
 #pragma unroll 1
-    for (int base = 0; base < nparts; base += 4 * kPairBlock) {
-        Partial p[4];
+    for (int base = 0; base < nparts; base += 8 * kPairBlock) {
+        Partial p[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
+            // unconditional loads (clamped index, nparts >= 1), then the
+            // neutral element past the end: a guarded load would wait alone
             const int ix = base + u * kPairBlock + (int)threadIdx.x;
-            p[u] = ix < nparts ? a.part[ix]
-                               : Partial{__builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0, kKeyNone};
+            p[u] = a.part[min(ix, nparts - 1)];
+            if (ix >= nparts) p[u] = Partial{__builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0, kKeyNone};
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             if (lex_less(p[u].r, p[u].i, p[u].j, best, bi, bj)) { best = p[u].r; bi = p[u].i; bj = p[u].j; }
             nres += p[u].n_rescored;
             nunits += p[u].n_units;
@@ -893,61 +896,131 @@ __global__ __launch_bounds__(kPairBlock) void k_prep(SweepArgs<TX> a, const doub
 
 // ------------------------------------------------------------------ the update
 
-// One wavefront: the paper's update of P in FP64, from the recorded pair:
+// v + (v of the exchange partner at distance 2^S inside the wavefront):
+// quad xor 1, quad xor 2, 16-lane rotation by 4 (the partner differs in bit
+// 2 and agrees below it), rotation by 8 (xor 8), then the permlane swaps.
+template <int S>
+__device__ __forceinline__ double xchg_add(double mine, double other) {
+    if constexpr (S == 0) return mine + dpp_f64<0xB1>(other);
+    else if constexpr (S == 1) return mine + dpp_f64<0x4E>(other);
+    else if constexpr (S == 2) return mine + dpp_f64<0x124>(other);
+    else return mine + dpp_f64<0x128>(other);
+}
+
+// Wavefront sums of v[0..NV-1] (NV <= 16), transposed: the exchange at
+// distance 2^s (s < H = ceil(log2 NV)) halves the values each lane carries
+// -- the lane keeps the half whose index has bit s equal to its lane's bit
+// s and receives its partner's share of that half -- and the later
+// exchanges add whole sums.  Lane L ends with the total of index L mod 2^H:
+// about a quarter of the exchanges of NV separate reductions.
+template <int NV>
+__device__ __forceinline__ double wave_sum_transposed(const double (&v)[NV]) {
+    static_assert(NV >= 1 && NV <= 16, "reduction batch");
+    constexpr int H = NV <= 1 ? 0 : NV <= 2 ? 1 : NV <= 4 ? 2 : NV <= 8 ? 3 : 4;
+    const int lane = threadIdx.x & (kWave - 1);
+    double c[1 << H];
+#pragma unroll
+    for (int e = 0; e < (1 << H); ++e) c[e] = e < NV ? v[e] : 0.0;
+#pragma unroll
+    for (int st = 0; st < H; ++st) {
+        const bool up = (lane >> st) & 1;
+#pragma unroll
+        for (int u = 0; u < (1 << (H - 1 - st)); ++u) {
+            const double lo = c[2 * u], hi = c[2 * u + 1];
+            const double mine = up ? hi : lo, other = up ? lo : hi;
+            if (st == 0) c[u] = xchg_add<0>(mine, other);
+            else if (st == 1) c[u] = xchg_add<1>(mine, other);
+            else if (st == 2) c[u] = xchg_add<2>(mine, other);
+            else c[u] = xchg_add<3>(mine, other);
+        }
+    }
+    double t = c[0];
+    if constexpr (H <= 0) t = xchg_add<0>(t, t);
+    if constexpr (H <= 1) t = xchg_add<1>(t, t);
+    if constexpr (H <= 2) t = xchg_add<2>(t, t);
+    if constexpr (H <= 3) t = xchg_add<3>(t, t);
+    t = pair_sum16(t);
+    return pair_sum32(t);
+}
+
+// v[0..NV-1] summed over the block, the same bits in every thread:
+// transposed wavefront sums, then the wavefronts' sums added in a fixed
+// order.  Every thread of the block must call it.  red holds two
+// alternating buffers (ph selects one and flips): a wavefront can rewrite a
+// buffer only after the next call's barrier, which every wavefront reaches
+// after reading it, so one barrier per call suffices.
+template <int NV>
+__device__ __forceinline__ void block_sum_many(double (&v)[NV], double (*red)[kPairBlock / kWave][16], int &ph) {
+    const double t = wave_sum_transposed<NV>(v);
+    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    if (lane < NV) red[ph][w][lane] = t;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < NV; ++e) v[e] = (red[ph][0][e] + red[ph][1][e]) + (red[ph][2][e] + red[ph][3][e]);
+    ph ^= 1;
+}
+__device__ __forceinline__ double block_sum(double x, double (*red)[kPairBlock / kWave][16], int &ph) {
+    double v[1] = {x};
+    block_sum_many<1>(v, red, ph);
+    return v[0];
+}
+
+// The whole block: the paper's update of P in FP64, from the recorded pair:
 //   c = P^T s;  t = first argmax |c_t|;
 //   if c = 0:   P' = [s, p_2, .., p_k]
 //   else:       v = P c; modified Gram-Schmidt on (v, p_1..p_k without p_t);
 //               u = unit((1-a) v + a (s - v))   [rule 1: unit vectors of v, s-v]
 //               P' = [u, q_2, .., q_k]
-// The vectors live in LDS (A: K x n, then s, v); lane l owns components
-// l, l+64, ...; every inner product is a wavefront sum.  Modified
+// The vectors live in LDS (A: K x n, then s, v); thread x owns components
+// x, x+256, ... of every vector and is the only one to touch them, so the
+// vectors need no barriers; every inner product is a block sum.  Modified
 // Gram-Schmidt runs right-looking: once q_m is final, every later vector
 // loses its component along q_m (per vector, the same sequence of
 // subtractions as the column-by-column form).  The independent inner
 // products of one step (the K entries of c; the projections of all later
 // vectors on q_m) are reduced together, so a step waits on two reductions
-// (|a_m| and the batch), not on one per vector.  The loop over m is not
-// unrolled: this code runs once per launch, and straight-line code is bound
-// by instruction fetch.
+// (|a_m| and the batch).  Every thread of the block must call this.
 template <int K, typename TX>
-__device__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
+__device__ __forceinline__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
                              double *__restrict__ P64t, double *__restrict__ P64r,
                              void *__restrict__ Pr, int pr_kind, double alpha, int rule,
                              DevResult *__restrict__ res, int64_t i, int64_t j, double *sm) {
-    const int lane = threadIdx.x & 63;
+    __shared__ double red[2][kPairBlock / kWave][16];
+    int ph = 0;
+    const int tid = threadIdx.x;
     double *A = sm;                       // K x n: P (loaded by the caller), then MGS vectors
     double *s = sm + (size_t)K * n;       // unit secant, later u
     double *v = s + n;                    // P P^T s
     double d2 = 0.0;
-    for (int l = lane; l < n; l += kWave) {
+    for (int l = tid; l < n; l += kPairBlock) {
         const double dl = (double)X[i * ldx + l] - (double)X[j * ldx + l];
         s[l] = dl;
         d2 = __builtin_fma(dl, dl, d2);
     }
-    const double d = sqrt(wave_sum_fast(d2));
-    // c = P^T s, t = first argmax |c_t| (every lane holds the same sums)
+    const double d = sqrt(block_sum(d2, red, ph));
+    // c = P^T s, t = first argmax |c_t| (every thread holds the same sums)
     double c[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) c[q] = 0.0;
-    for (int l = lane; l < n; l += kWave) {
+    for (int l = tid; l < n; l += kPairBlock) {
         const double sl = s[l] / d;
         s[l] = sl;
 #pragma unroll
         for (int q = 0; q < K; ++q) c[q] = __builtin_fma(A[(size_t)q * n + l], sl, c[q]);
     }
-    wave_sum_many<K>(c);
+    block_sum_many<K>(c, red, ph);
     int t = 0;
     double cmax = -1.0;
 #pragma unroll
     for (int q = 0; q < K; ++q)
         if (fabs(c[q]) > cmax) { cmax = fabs(c[q]); t = q; }
-    if (lane == 0) res->t = t;
+    if (tid == 0) res->t = t;
 
     if (cmax == 0.0) {
-        for (int l = lane; l < n; l += kWave) A[l] = s[l];
+        for (int l = tid; l < n; l += kPairBlock) A[l] = s[l];
     } else {
         // v = P c; MGS input order (v, p_1..p_{t-1}, p_{t+1}..p_k), in place
-        for (int l = lane; l < n; l += kWave) {
+        for (int l = tid; l < n; l += kPairBlock) {
             double acc = 0.0;
 #pragma unroll
             for (int q = 0; q < K; ++q) acc = __builtin_fma(A[(size_t)q * n + l], c[q], acc);
@@ -960,39 +1033,47 @@ __device__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
         for (int m = 0; m < K; ++m) {
             double *am = A + (size_t)m * n;
             double nn = 0.0;
-            for (int l = lane; l < n; l += kWave) nn = __builtin_fma(am[l], am[l], nn);
-            const double nrm = sqrt(wave_sum_fast(nn));
+            for (int l = tid; l < n; l += kPairBlock) nn = __builtin_fma(am[l], am[l], nn);
+            const double nrm = sqrt(block_sum(nn, red, ph));
             if (m == 0) vnorm = nrm;
+            if (m + 1 == K) {
+                for (int l = tid; l < n; l += kPairBlock) am[l] = am[l] / nrm;
+                break;
+            }
+            // every row's inner product with q_m, without branches (rows
+            // up to m are final: their products go unused and the select
+            // below rewrites them unchanged)
             double dots[K];
 #pragma unroll
             for (int jv = 0; jv < K; ++jv) dots[jv] = 0.0;
-            for (int l = lane; l < n; l += kWave) {
+            for (int l = tid; l < n; l += kPairBlock) {
                 const double q = am[l] / nrm;
                 am[l] = q;
 #pragma unroll
-                for (int jv = 0; jv < K; ++jv)
-                    if (jv > m) dots[jv] = __builtin_fma(q, A[(size_t)jv * n + l], dots[jv]);
+                for (int jv = 0; jv < K; ++jv) dots[jv] = __builtin_fma(q, A[(size_t)jv * n + l], dots[jv]);
             }
-            wave_sum_many<K>(dots, m + 1);
-            for (int l = lane; l < n; l += kWave) {
+            block_sum_many<K>(dots, red, ph);
+            for (int l = tid; l < n; l += kPairBlock) {
                 const double q = am[l];
+                double x[K];   // every row read before any is written back
 #pragma unroll
-                for (int jv = 0; jv < K; ++jv)
-                    if (jv > m) A[(size_t)jv * n + l] = A[(size_t)jv * n + l] - dots[jv] * q;
+                for (int jv = 0; jv < K; ++jv) x[jv] = A[(size_t)jv * n + l];
+#pragma unroll
+                for (int jv = 0; jv < K; ++jv) A[(size_t)jv * n + l] = jv > m ? x[jv] - dots[jv] * q : x[jv];
             }
         }
         // the alpha shift toward the worst secant
         double wn = 1.0;
         if (rule == SAP_STEP_NORMALIZED) {
             double acc = 0.0;
-            for (int l = lane; l < n; l += kWave) {
+            for (int l = tid; l < n; l += kPairBlock) {
                 const double w = s[l] - v[l];
                 acc = __builtin_fma(w, w, acc);
             }
-            wn = sqrt(wave_sum_fast(acc));
+            wn = sqrt(block_sum(acc, red, ph));
         }
         double un = 0.0;
-        for (int l = lane; l < n; l += kWave) {
+        for (int l = tid; l < n; l += kPairBlock) {
             double u;
             if (rule == SAP_STEP_NORMALIZED)
                 u = (1.0 - alpha) * (v[l] / vnorm) + (wn > 0.0 ? alpha * ((s[l] - v[l]) / wn) : 0.0);
@@ -1001,11 +1082,11 @@ __device__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
             s[l] = u;
             un = __builtin_fma(u, u, un);
         }
-        const double unrm = sqrt(wave_sum_fast(un));
-        for (int l = lane; l < n; l += kWave) A[l] = s[l] / unrm;
+        const double unrm = sqrt(block_sum(un, red, ph));
+        for (int l = tid; l < n; l += kPairBlock) A[l] = s[l] / unrm;
     }
     // write back: master (K x n), row-major FP64 copy, and the plain pass's copy
-    for (int l = lane; l < n; l += kWave) {
+    for (int l = tid; l < n; l += kPairBlock) {
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             const double pv = A[(size_t)q * n + l];
@@ -1154,17 +1235,37 @@ __global__ __launch_bounds__(kPairBlock) void k_select(SweepArgs<TX> a, int nsho
     extern __shared__ double sm_dyn[];
     // P into LDS now, so that its loads overlap the selection (the block
     // barriers inside select_min order these writes before the update)
-    for (int e = threadIdx.x; e < K * a.n; e += kPairBlock) sm_dyn[e] = a.P64t[e];
+    // (eight loads in flight per thread before any is stored)
+    if (do_step) {
+        const int kn = K * a.n;
+#pragma unroll 1
+        for (int e0 = threadIdx.x; e0 < kn; e0 += 8 * kPairBlock) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * kPairBlock;
+                t[u] = e < kn ? a.P64t[e] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * kPairBlock;
+                if (e < kn) sm_dyn[e] = t[u];
+            }
+        }
+    }
     const int2 ij = select_min<K, TX, FUSED>(a, a.npass + nshort);
-    if (do_step && ij.x >= 0 && threadIdx.x < kWave) {
-        // registers when every vector fits one 64-lane slice and K is
-        // small, LDS otherwise
-        if (K <= 8 && a.n <= 64)
-            apply_update_reg<K, 1, TX>(a.X, a.ldx, a.n, sm_dyn, P64t, P64r, Pr, pr_kind, alpha, rule,
-                                       a.res, ij.x, ij.y);
-        else
+    if (do_step && ij.x >= 0) {
+        // one wavefront with the vectors in registers when every vector
+        // fits one 64-lane slice and K is small, the whole block over LDS
+        // otherwise
+        if (K <= 8 && a.n <= 64) {
+            if (threadIdx.x < kWave)
+                apply_update_reg<K, 1, TX>(a.X, a.ldx, a.n, sm_dyn, P64t, P64r, Pr, pr_kind, alpha, rule,
+                                           a.res, ij.x, ij.y);
+        } else {
             apply_update<K, TX>(a.X, a.ldx, a.n, P64t, P64r, Pr, pr_kind, alpha, rule, a.res, ij.x,
                                 ij.y, sm_dyn);
+        }
     }
 }
 
