@@ -40,7 +40,8 @@ def log(msg):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pass_fused_trig64_N4000_n64_k6_traffic.txt")
-KERNEL_SOURCES = ("paper_1807_03425_amd/csrc/sap_iter.hip", "paper_1807_03425_amd/csrc/sap_common.h")
+KERNEL_SOURCES = ("paper_1807_03425_amd/csrc/sap_iter.hip", "paper_1807_03425_amd/csrc/sap_common.h",
+                  "paper_1807_03425_amd/csrc/sap_api.hip")
 
 
 def measured_traffic():

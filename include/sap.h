@@ -77,8 +77,9 @@ enum { SAP_STEP_LITERAL = 0, SAP_STEP_NORMALIZED = 1 };  /* reading of the shift
  *         (the paper's wording); SAP_STEP_NORMALIZED combines their unit
  *         vectors.
  *   close_d: fused form only; pairs with d < close_d are evaluated in FP64
- *         every iteration.  < 0 selects it automatically from the coarse
- *         error bound (see sap_info).  close_cap bounds that list (0 = 1<<20);
+ *         every iteration.  < 0 selects it automatically: the cutoff at
+ *         which the coarse error bound e_abs (see sap_info) is about 4e-6.
+ *         close_cap bounds that list (0 = min(2^20, max(1024, p / n)));
  *         an automatic cutoff is lowered until the list fits, an explicit one
  *         that does not fit fails with SAP_ERR_CAPACITY. */
 typedef struct {

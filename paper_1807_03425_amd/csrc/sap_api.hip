@@ -20,6 +20,27 @@
 
 using namespace sap;
 
+// Grid sizing of the fused pass: half-tiles per pass block (the blocks
+// stride over the rest) and short pairs per short-pair block.
+#ifndef SAP_HALVES_PER_BLOCK
+#define SAP_HALVES_PER_BLOCK 8
+#endif
+#ifndef SAP_SHORT_PER_BLOCK
+#define SAP_SHORT_PER_BLOCK 64
+#endif
+// Automatic short-pair cap: p / (SAP_CLOSE_CAP_DIV n) pairs, within
+// [1024, 2^20] (a short pair and a rescored window pair cost about the same:
+// one FP64 product over n).
+#ifndef SAP_CLOSE_CAP_DIV
+#define SAP_CLOSE_CAP_DIV 1
+#endif
+// Automatic short-pair cutoff: the absolute coarse error it aims at.  A
+// tighter target mostly adds short pairs (each an FP64 product over n every
+// iteration) while the rescoring window it narrows holds few pairs.
+#ifndef SAP_EABS_TARGET
+#define SAP_EABS_TARGET 4e-6
+#endif
+
 // ---------------------------------------------------------------- context
 
 struct sap_ctx {
@@ -296,10 +317,10 @@ static sap_status init_fused(sap_ctx *h) {
 
     // Coarse error: ||y~_i - y_i|| <= u32 ||y_i|| + FP64 terms <= R (u32 + ...),
     // so |r~ - r| <= 2 R (u32 + ...) / d.  The automatic cutoff aims at an
-    // absolute error of 1e-6 for every pair left to the coarse pass.
+    // absolute error of SAP_EABS_TARGET for every pair left to the coarse pass.
     const double delta = h->radius * (kU32 * 1.001 + (h->n + 2) * std::sqrt((double)h->k) * kU64 * 4.0);
     const bool automatic = h->cfg.close_d < 0.0;
-    double dtarget = automatic ? 2.0 * delta / 1e-6 : h->cfg.close_d;
+    double dtarget = automatic ? 2.0 * delta / SAP_EABS_TARGET : h->cfg.close_d;
     std::vector<float> ladder(64);
     for (int m = 0; m < 64; ++m) {
         const double D = dtarget * std::pow(2.0, -m / 4.0);
@@ -324,7 +345,7 @@ static sap_status init_fused(sap_ctx *h) {
 
     const int64_t cap = h->cfg.close_cap > 0
                             ? h->cfg.close_cap
-                            : std::min<int64_t>(1 << 20, std::max<int64_t>(1024, h->p / (4 * h->n)));
+                            : std::min<int64_t>(1 << 20, std::max<int64_t>(1024, h->p / (SAP_CLOSE_CAP_DIV * h->n)));
     // count(1/d^2 > ladder[m]) = sum of bins m..63
     int msel = -1;
     uint64_t tail = 0;
@@ -405,10 +426,10 @@ static sap_status init_fused(sap_ctx *h) {
     h->e_rel = (h->k + 4) * kU32;
     // at least two half-tiles per wavefront (the next one's loads overlap the
     // current one's arithmetic), four wavefronts per block
-    h->pass_grid = (int)std::min<int64_t>(ceil_div(2 * h->ntiles, 8), 8192);
+    h->pass_grid = (int)std::min<int64_t>(ceil_div(2 * h->ntiles, SAP_HALVES_PER_BLOCK), 8192);
     // iteration: 64 short pairs per block (16 per wavefront, on the matrix
     // cores); the soft-min's short-pair blocks use the same grid size
-    h->short_grid = h->nclose > 0 ? (int)std::min<int64_t>(ceil_div(h->nclose, 64), 1024) : 0;
+    h->short_grid = h->nclose > 0 ? (int)std::min<int64_t>(ceil_div(h->nclose, SAP_SHORT_PER_BLOCK), 1024) : 0;
     return SAP_OK;
 }
 

@@ -242,7 +242,11 @@ __device__ __forceinline__ void plain_r2(const T *__restrict__ S, int64_t pcols,
     for (int l = 0; l < n; ++l) {
         T s[4];
         Vec4<T>::load(sp + (int64_t)l * pcols, s);
-        const T *pl = Pr + l * K;
+        // P is read-only during the pass: its uniform row goes through the
+        // constant address space (scalar loads), so it does not hold up the
+        // vector loads of the next rows of S
+        const __attribute__((address_space(4))) T *pl =
+            (const __attribute__((address_space(4))) T *)(Pr + l * K);
 #pragma unroll
         for (int c = 0; c < K; ++c) {
             const T p = pl[c];
