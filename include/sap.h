@@ -138,7 +138,10 @@ sap_status sap_step(sap_handle h, sap_min_result *out_or_null);
 /* Algorithm 1 from the current P: iters updates and iters+1 evaluations (the
  * last one scores the returned P).  Traces are device buffers of iters+1
  * entries: min (FP64), (i, j) as 2 int64 per entry, certified (int32).
- * ij_trace and cert_trace may be NULL.  Asynchronous. */
+ * ij_trace and cert_trace may be NULL.  Asynchronous.  The fused form runs
+ * each iteration's selection and update in the same launch as the next
+ * iteration's Y GEMM (two launches per iteration); results are those of
+ * iters calls of sap_step followed by sap_min_secant. */
 sap_status sap_run(sap_handle h, int32_t iters, double *min_trace,
                    int64_t *ij_trace, int32_t *cert_trace);
 
@@ -186,12 +189,14 @@ sap_status sap_softmin_bwd(sap_handle h, const float *P, double tau,
  * handle's stream; the work itself is unchanged).  sap_profile_read
  * synchronises, returns the summed durations and launch counts since the
  * last read, and restarts the accumulation.
- * Slots: 0 = Y GEMM (fused form), 1 = pair pass (with the fused form's FP64
- * short pairs), 2 = selection: window, FP64 rescoring, record and update;
- * soft-min:
+ * Slots: 0 = Y GEMM (fused form), 1 = pair pass (with the window pairs'
+ * FP64 rescoring and the fused form's FP64 short pairs), 2 = selection:
+ * record and update; soft-min:
  * 3 = forward tile pass, 4 = backward tile pass, 5 = the other soft-min
  * launches (P load, Y GEMM, short pairs, merges, the (X - mean)^T Z
- * contraction); 6 and 7 are unused. */
+ * contraction); 6 = sap_run in the fused form: selection, record and
+ * update fused with the next iteration's Y GEMM (slot 0 then counts the
+ * run's first GEMM only); 7 is unused. */
 typedef struct {
     double ms[8];
     int64_t launches[8];

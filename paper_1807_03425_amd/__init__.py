@@ -60,7 +60,7 @@ class sap_profile_t(C.Structure):
     _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
 
 
-PROFILE_SLOTS = ("gemm", "pass", "select", "sm_fwd", "sm_bwd", "sm_other")
+PROFILE_SLOTS = ("gemm", "pass", "select", "sm_fwd", "sm_bwd", "sm_other", "select_gemm")
 
 _lib: Optional[C.CDLL] = None
 

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include <hip/hip_ext.h>
@@ -71,7 +72,8 @@ struct sap_ctx {
     void *d_Pr = nullptr;
 
     // common
-    double *d_P64t = nullptr;
+    double *d_P64t = nullptr;       // the current P (FP64 master, K x n)
+    double *d_P64t_alt = nullptr;   // fused: the other P buffer, written by k_selprep
     double *d_P64r = nullptr;
     double *d_mu = nullptr;
     DevState *d_st = nullptr;
@@ -499,26 +501,39 @@ static SweepArgs<TX> sweep_args(sap_ctx *h, double *tr_min, int64_t *tr_ij, int3
 
 // Enqueue one evaluation (+ update when do_step).
 template <typename TX>
-static sap_status launch_iteration(sap_ctx *h, int do_step, double *tr_min, int64_t *tr_ij,
-                                   int32_t *tr_cert, int it) {
+static sap_status launch_prep(sap_ctx *h) {
+    const int K = h->k;
+    const SweepArgs<TX> a = sweep_args<TX>(h, nullptr, nullptr, nullptr, 0);
+    const dim3 g0((unsigned)(h->Npad / 64)), blk(kPairBlock);
+    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 0, "k_prep", k_prep<K, TX>, g0, blk, 0, a, h->d_mu, h->d_Y, h->Npad)));
+    return SAP_OK;
+}
+
+template <typename TX>
+static sap_status launch_pass(sap_ctx *h) {
     const int K = h->k;
     const bool fused = h->cfg.form == SAP_FUSED;
-    const SweepArgs<TX> a = sweep_args<TX>(h, tr_min, tr_ij, tr_cert, it);
+    const SweepArgs<TX> a = sweep_args<TX>(h, nullptr, nullptr, nullptr, 0);
     const int nshort = fused ? h->short_grid : 0;
-    const dim3 blk(kPairBlock);
-    if (fused) {
-        const dim3 g0((unsigned)(h->Npad / 64));
-        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 0, "k_prep", k_prep<K, TX>, g0, blk, 0, a, h->d_mu,
-                                         h->d_Y, h->Npad)));
-    }
-    const dim3 g1((unsigned)(h->pass_grid + nshort));
+    const dim3 g1((unsigned)(h->pass_grid + nshort)), blk(kPairBlock);
     if (fused) {
         SAP_DISPATCH_K(K, SAP_TRY(launch(h, 1, "k_pass", k_pass<K, TX, true>, g1, blk, 0, a, nshort)));
     } else {
         SAP_DISPATCH_K(K, SAP_TRY(launch(h, 1, "k_pass", k_pass<K, TX, false>, g1, blk, 0, a, 0)));
     }
+    return SAP_OK;
+}
+
+template <typename TX>
+static sap_status launch_select(sap_ctx *h, int do_step, double *tr_min, int64_t *tr_ij, int32_t *tr_cert,
+                                int it) {
+    const int K = h->k;
+    const bool fused = h->cfg.form == SAP_FUSED;
+    const SweepArgs<TX> a = sweep_args<TX>(h, tr_min, tr_ij, tr_cert, it);
+    const int nshort = fused ? h->short_grid : 0;
     const int pr_kind = fused ? 0 : (h->cfg.dtype == SAP_F64 ? 2 : 1);
     const uint32_t lds = (uint32_t)h->tail_lds;
+    const dim3 blk(kPairBlock);
     if (fused) {
         SAP_DISPATCH_K(K, SAP_TRY(launch(h, 2, "k_select", k_select<K, TX, true>, dim3(1), blk, lds,
                                          a, nshort, h->d_P64t, h->d_P64r, h->d_Pr, pr_kind,
@@ -529,6 +544,52 @@ static sap_status launch_iteration(sap_ctx *h, int do_step, double *tr_min, int6
                                          h->cfg.alpha, h->cfg.rule, do_step)));
     }
     return SAP_OK;
+}
+
+// Fused form: selection + update of iteration it and the Y GEMM of the next
+// P in one launch; the next P goes to the other buffer, which becomes the
+// current one.
+template <typename TX>
+static sap_status launch_selprep(sap_ctx *h, double *tr_min, int64_t *tr_ij, int32_t *tr_cert, int it) {
+    const int K = h->k;
+    const SweepArgs<TX> a = sweep_args<TX>(h, tr_min, tr_ij, tr_cert, it);
+    const dim3 g0((unsigned)(h->Npad / 64)), blk(kPairBlock);
+    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 6, "k_selprep", k_selprep<K, TX>, g0, blk, (uint32_t)h->tail_lds, a,
+                                     h->short_grid, h->d_P64t_alt, h->cfg.alpha, h->cfg.rule, h->d_mu,
+                                     h->d_Y, h->Npad)));
+    std::swap(h->d_P64t, h->d_P64t_alt);
+    return SAP_OK;
+}
+
+// One evaluation (+ update when do_step): GEMM (fused), pass, selection.
+template <typename TX>
+static sap_status launch_iteration(sap_ctx *h, int do_step, double *tr_min, int64_t *tr_ij,
+                                   int32_t *tr_cert, int it) {
+    if (h->cfg.form == SAP_FUSED) SAP_TRY(launch_prep<TX>(h));
+    SAP_TRY(launch_pass<TX>(h));
+    return launch_select<TX>(h, do_step, tr_min, tr_ij, tr_cert, it);
+}
+
+// iters updates and a final evaluation.  Fused form with a small GEMM grid:
+// the GEMM once, then per iteration the pass and the fused
+// selection/update/GEMM (two launches).  Every block of the fused kernel
+// reads all block results, so larger grids (more than 16 MB of such reads
+// per iteration) keep the three launches.
+template <typename TX>
+static sap_status launch_run(sap_ctx *h, int32_t iters, double *tr_min, int64_t *tr_ij, int32_t *tr_cert) {
+    const int64_t reads = (h->Npad / 64) * (int64_t)(h->pass_grid + h->short_grid) * (int64_t)sizeof(Partial);
+    if (h->cfg.form != SAP_FUSED || reads > (16 << 20)) {
+        for (int32_t it = 0; it <= iters; ++it)
+            SAP_TRY(launch_iteration<TX>(h, it < iters ? 1 : 0, tr_min, tr_ij, tr_cert, it));
+        return SAP_OK;
+    }
+    SAP_TRY(launch_prep<TX>(h));
+    for (int32_t it = 0; it < iters; ++it) {
+        SAP_TRY(launch_pass<TX>(h));
+        SAP_TRY(launch_selprep<TX>(h, tr_min, tr_ij, tr_cert, it));
+    }
+    SAP_TRY(launch_pass<TX>(h));
+    return launch_select<TX>(h, 0, tr_min, tr_ij, tr_cert, iters);
 }
 
 static sap_status enqueue_eval(sap_ctx *h, int do_step, double *tr_min, int64_t *tr_ij,
@@ -707,6 +768,8 @@ sap_status sap_init(const sap_config *cfg, const void *X, int64_t ldx, const dou
     if (h->kept == 0) return bail(fail(h, SAP_ERR_NO_PAIRS, "every pair is a duplicate or shorter than min_len"));
     if ((s = dalloc(h, &h->d_part, sizeof(Partial) * (size_t)(h->pass_grid + h->short_grid))) != SAP_OK)
         return bail(s);
+    if (cfg->form == SAP_FUSED && (s = dalloc(h, &h->d_P64t_alt, sizeof(double) * h->n * h->k)) != SAP_OK)
+        return bail(s);
     if ((s = load_P(h, P0)) != SAP_OK) return bail(s);
     h->tail_lds = sizeof(double) * ((size_t)h->k * h->n + 2 * (size_t)h->n);
     e = hipSuccess;
@@ -715,7 +778,13 @@ sap_status sap_init(const sap_config *cfg, const void *X, int64_t ldx, const dou
                               reinterpret_cast<const void *>(&k_select<K, float, false>),
                               reinterpret_cast<const void *>(&k_select<K, double, true>),
                               reinterpret_cast<const void *>(&k_select<K, double, false>)};
+        const void *fns_sp[2] = {reinterpret_cast<const void *>(&k_selprep<K, float>),
+                                 reinterpret_cast<const void *>(&k_selprep<K, double>)};
         for (const void *f : fns)
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)h->tail_lds);
+        for (const void *f : fns_sp)
             if (e == hipSuccess)
                 e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)h->tail_lds);
@@ -746,9 +815,8 @@ sap_status sap_run(sap_handle h, int32_t iters, double *min_trace, int64_t *ij_t
     SAP_TRY(usable(h));
     if (iters < 0) return fail(h, SAP_ERR_INVALID_ARG, "iters must be >= 0");
     if (!min_trace) return fail(h, SAP_ERR_INVALID_ARG, "min_trace must not be NULL");
-    for (int32_t it = 0; it <= iters; ++it)
-        SAP_TRY(enqueue_eval(h, it < iters ? 1 : 0, min_trace, ij_trace, cert_trace, it));
-    return SAP_OK;
+    if (h->cfg.dtype == SAP_F64) return launch_run<double>(h, iters, min_trace, ij_trace, cert_trace);
+    return launch_run<float>(h, iters, min_trace, ij_trace, cert_trace);
 }
 
 sap_status sap_get_P(sap_handle h, double *P_out) {

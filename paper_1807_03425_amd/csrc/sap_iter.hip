@@ -272,20 +272,38 @@ __device__ __forceinline__ uint32_t key_of(T r2) {
 // ------------------------------------------------------------------ FP64 scores
 
 // FP64 r of pair (i, j) from X: ||P^T (x_i - x_j)|| / ||x_i - x_j||, with
-// P (K x n, FP64) in LDS.  Wavefront-cooperative (lanes split the n
-// components); every lane returns the same value.
+// P (K x n, FP64, component-contiguous rows).  Wavefront-cooperative (lanes
+// split the n components; every lane returns the same value).  The
+// components come in groups of U per lane whose loads (clamped index,
+// masked afterwards) are all issued before any is used.
 template <int K, typename TX>
-__device__ double exact_r_wave(const TX *__restrict__ X, int64_t ldx, int n,
-                               const double *P64t, int64_t i, int64_t j) {
+__device__ __forceinline__ double exact_r_wave(const TX *__restrict__ X, int64_t ldx, int n,
+                                               const double *P64t, int64_t i, int64_t j) {
+    constexpr int U = K <= 8 ? 4 : 2;
     const int lane = threadIdx.x & 63;
+    const TX *xi = X + i * ldx, *xj = X + j * ldx;
     double v[K + 1];
 #pragma unroll
     for (int q = 0; q <= K; ++q) v[q] = 0.0;
-    for (int l = lane; l < n; l += kWave) {
-        const double dl = (double)X[i * ldx + l] - (double)X[j * ldx + l];
-        v[K] = __builtin_fma(dl, dl, v[K]);
+#pragma unroll 1
+    for (int base = 0; base < n; base += U * kWave) {
+        const int l0 = base + lane;
+        double a[U], b[U], p[U][K];
 #pragma unroll
-        for (int q = 0; q < K; ++q) v[q] = __builtin_fma(P64t[(int64_t)q * n + l], dl, v[q]);
+        for (int u = 0; u < U; ++u) {
+            const int lc = min(l0 + u * kWave, n - 1);
+            a[u] = (double)xi[lc];
+            b[u] = (double)xj[lc];
+#pragma unroll
+            for (int q = 0; q < K; ++q) p[u][q] = P64t[(int64_t)q * n + lc];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double dl = l0 + u * kWave < n ? a[u] - b[u] : 0.0;
+            v[K] = __builtin_fma(dl, dl, v[K]);
+#pragma unroll
+            for (int q = 0; q < K; ++q) v[q] = __builtin_fma(p[u][q], dl, v[q]);
+        }
     }
     wave_sum_many<K + 1>(v);
     double r2 = 0.0;
@@ -464,32 +482,18 @@ struct SweepArgs {
     int it;
 };
 
-// Element e (runtime) of a lane's key array, as a binary tree of selects
-// over constant indices: no dynamic register indexing, so the array stays in
-// registers.
-template <int LO, int NN, int NK>
-__device__ __forceinline__ uint32_t key_sel(const uint32_t (&key)[NK], int e) {
-    if constexpr (NN == 1) {
-        return key[LO];
-    } else {
-        return e < LO + NN / 2 ? key_sel<LO, NN / 2, NK>(key, e) : key_sel<LO + NN / 2, NN / 2, NK>(key, e);
-    }
-}
-template <int NK>
-__device__ __forceinline__ uint32_t key_at(const uint32_t (&key)[NK], int e) {
-    return key_sel<0, NK, NK>(key, e);
-}
-
-// Candidates of a pass block.  Within a work item (a half-tile or a chunk)
-// whose smallest key is m, every pair with key <= T2(m) is a candidate: the
-// global window is T2(global minimum) <= T2(block minimum) <= T2(m), so every
-// window pair of the iteration is a candidate of its own work item.  Each
-// wavefront appends its candidates (i, j, key) to its LDS list during the
-// pass; after the pass the block keeps those with key <= T2(block minimum)
-// and rescores them in FP64 (wavefront-cooperatively), re-checking each
-// coarse value against the bound.  A full list is first pruned to the
-// wavefront's own running window; if it is still full, the candidate is
-// dropped and the block's result marked uncertified (never silently).
+// Candidates of a pass block.  The block keeps its running minimum key in
+// LDS; after a work item (a half-tile or a chunk) with smallest key m it is
+// run = min(run, m), and every pair of the item with key <= T2(run) is a
+// candidate.  The global window T2(global minimum) <= T2(block minimum) <=
+// T2(run) at every point of the sweep, so every window pair of the
+// iteration is a candidate of its own work item.  Each wavefront appends its
+// candidates (i, j, key) to its LDS list during the pass; after the pass the
+// block keeps those with key <= T2(block minimum) and rescores them in FP64
+// (wavefront-cooperatively), re-checking each coarse value against the
+// bound.  A full list is first pruned to the current window; if it is still
+// full, the candidate is dropped and the block's result marked uncertified
+// (never silently).
 constexpr int kCandCap = 128;   // candidates per wavefront
 
 struct CandList {
@@ -505,50 +509,73 @@ struct WaveBest {
     int32_t i, j, nwin, nviol, nunits;
 };
 
-// Append the set bits of the lanes' masks `bits` (slot e of lane l):
-// keyof(l, e) and pair(l, e) give its key and (i, j) from wavefront-uniform
-// arguments.  kmin: the wavefront's running minimum (its window prunes a
-// full list).
-template <typename TX, typename KeyOf, typename PairOf>
-__device__ __forceinline__ void append_cands(const SweepArgs<TX> &a, CandList &cl, uint32_t bits,
-                                             uint32_t kmin, KeyOf keyof, PairOf pair, WaveBest &wb) {
+// Append the lanes' keys that are <= T2 (the window of the block's running
+// minimum) to the wavefront's list.  key[e] belongs to the lane's pair
+// pair(e, i, j); lmin is the lane's smallest key.  The few lanes holding
+// candidates write their own entries, at offsets from a running count over
+// those lanes, so no key has to move between lanes.  A full list is first
+// pruned to T2; entries that still do not fit are counted as lost.
+template <int NK, typename PairOf>
+__device__ __forceinline__ void emit_cands(CandList &cl, const uint32_t (&key)[NK], uint32_t lmin,
+                                           uint32_t T2, PairOf pair, WaveBest &wb) {
     const int lane = threadIdx.x & 63;
-    uint64_t lanes = __ballot(bits != 0);
-    if (lanes) ++wb.nunits;
+    uint32_t bits = 0;
+    if (lmin <= T2) {
+#pragma unroll
+        for (int e = 0; e < NK; ++e) bits |= (key[e] <= T2 ? 1u : 0u) << e;
+    }
+    const int cnt = __builtin_popcount(bits);
+    uint64_t lanes = __ballot(cnt > 0);
+    if (!lanes) return;
+    ++wb.nunits;
+    int base = 0, tot = 0;
 #pragma unroll 1
     while (lanes) {
         const int ln = __builtin_ctzll(lanes);
         lanes &= lanes - 1;
-        uint32_t lb = __shfl(bits, ln, kWave);
-#pragma unroll 1
-        while (lb) {
-            const int e = __builtin_ctz(lb);
-            lb &= lb - 1;
-            const uint32_t kv = keyof(ln, e);
-            if (cl.n == kCandCap) {
-                // prune to the running window (one lane, in order; rare)
-                const uint32_t T2run = item_window(kmin, a.wa, a.wb);
-                __builtin_amdgcn_wave_barrier();
-                if (lane == 0) {
-                    int w = 0;
-                    for (int c = 0; c < kCandCap; ++c)
-                        if (cl.key[c] <= T2run) { cl.ij[w] = cl.ij[c]; cl.key[w] = cl.key[c]; ++w; }
-                    *cl.cnt = w;
+        if (lane == ln) base = tot;
+        tot += __builtin_amdgcn_readlane(cnt, ln);
+    }
+    if (cl.n + tot > kCandCap) {
+        // prune to the current window (one lane, in order; rare)
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+            int w = 0;
+            for (int c = 0; c < cl.n; ++c)
+                if (cl.key[c] <= T2) { cl.ij[w] = cl.ij[c]; cl.key[w] = cl.key[c]; ++w; }
+            *cl.cnt = w;
+        }
+        __builtin_amdgcn_wave_barrier();
+        cl.n = __builtin_amdgcn_readfirstlane(*cl.cnt);
+    }
+    if (bits) {
+        int pos = cl.n + base;
+#pragma unroll
+        for (int e = 0; e < NK; ++e) {
+            if ((bits >> e) & 1u) {
+                if (pos < kCandCap) {
+                    int32_t i, j;
+                    pair(e, i, j);
+                    cl.ij[pos] = make_int2(i, j);
+                    cl.key[pos] = key[e];
                 }
-                __builtin_amdgcn_wave_barrier();
-                cl.n = __builtin_amdgcn_readfirstlane(*cl.cnt);
-                __builtin_amdgcn_wave_barrier();
-            }
-            if (cl.n < kCandCap) {
-                int32_t i, j;
-                pair(ln, e, i, j);
-                if (lane == 0) { cl.ij[cl.n] = make_int2(i, j); cl.key[cl.n] = kv; }
-                ++cl.n;
-            } else {
-                ++cl.lost;
+                ++pos;
             }
         }
     }
+    __builtin_amdgcn_wave_barrier();
+    const int room = kCandCap - cl.n;
+    if (tot > room) cl.lost += tot - room;
+    cl.n += tot < room ? tot : room;
+}
+
+// The block's running minimum key, shared in LDS: after a work item with
+// smallest key m, returns min(previous running minimum, m) and records it.
+__device__ __forceinline__ uint32_t block_run_min(uint32_t *s_run, uint32_t m) {
+    uint32_t old = 0;
+    if ((threadIdx.x & 63) == 0) old = atomicMin(s_run, m);
+    old = __builtin_amdgcn_readfirstlane(old);
+    return old < m ? old : m;
 }
 
 // After the pass loop: keep the candidates with key <= T2b, rescore them.
@@ -574,13 +601,15 @@ __device__ __forceinline__ void rescore_cands(const SweepArgs<TX> &a, const Cand
 // result goes to its Partial slot.
 template <int K, typename TX>
 __device__ __forceinline__ void finish_pass_block(const SweepArgs<TX> &a, const CandList &cl,
-                                                  uint32_t kmin, WaveBest &wb, Partial *out) {
-    __shared__ uint32_t s_km[kPairBlock / kWave];
+                                                  uint32_t kmin, const uint32_t *s_run, WaveBest &wb,
+                                                  Partial *out) {
+    // rescore now, against the window of the block's running minimum as it
+    // stands (never below the final block minimum, so this covers the block
+    // window's share of the list), overlapping the sweeps of the block's
+    // other wavefronts
+    const uint32_t run = __builtin_amdgcn_readfirstlane(*(const volatile uint32_t *)s_run);
+    if (run < 0x7f800000u) rescore_cands<K, TX>(a, cl, item_window(run, a.wa, a.wb), wb);
     const int lane = threadIdx.x & 63;
-    if (lane == 0) s_km[threadIdx.x >> 6] = kmin;
-    __syncthreads();
-    const uint32_t kb = min(min(s_km[0], s_km[1]), min(s_km[2], s_km[3]));
-    if (kb < 0x7f800000u) rescore_cands<K, TX>(a, cl, item_window(kb, a.wa, a.wb), wb);
     block_reduce_partial(wb.r, wb.i, wb.j, lane == 0 ? wb.nwin : 0, lane == 0 ? wb.nunits : 0,
                          lane == 0 ? wb.nviol : 0, kmin, out);
 }
@@ -592,8 +621,9 @@ __device__ __forceinline__ void finish_pass_block(const SweepArgs<TX> &a, const 
 // at once, before any is used; the y_i rows go through the wavefront's own
 // LDS slice (read back as broadcasts; no other wavefront touches it, so no
 // block barrier).
-// Per pair: K subtractions, K FMAs, one multiply, one unsigned min, one
-// compare against the half-tile's window.  Candidates are rescored after the
+// Per pair: K subtractions, K FMAs, one multiply, one unsigned min.  Only a
+// half-tile whose minimum lies inside the window of the block's running
+// minimum is scanned for candidates (emit_cands); they are rescored after the
 // loop (finish_pass_block).
 template <int K, typename TX>
 __device__ void fused_pass_block(const SweepArgs<TX> &a, int pb) {
@@ -601,18 +631,18 @@ __device__ void fused_pass_block(const SweepArgs<TX> &a, int pb) {
     __shared__ int2 s_cij[kPairBlock / kWave][kCandCap];
     __shared__ uint32_t s_ckey[kPairBlock / kWave][kCandCap];
     __shared__ int s_ccnt[kPairBlock / kWave];
-    // the half-tile's keys: lane l's 32 at l*36 (16-byte rows, padded)
-    __shared__ uint4 s_kb[kPairBlock / kWave][kWave * 9];
+    __shared__ uint32_t s_run;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nw = (int64_t)a.npass * (kPairBlock / kWave);
     const int kp = a.kp;
-    uint4 *kb4 = s_kb[wv];
     float4 *yl = s_y[wv];
+    if (threadIdx.x == 0) s_run = kKeyNone;
+    __syncthreads();
     const int nf4 = 8 * kp;                  // float4 count of 32 rows of Y (<= 128)
     WaveBest wb{__builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0};
     CandList cl{s_cij[wv], s_ckey[wv], &s_ccnt[wv], 0, 0};
-    uint32_t kmin = kKeyNone, T2run = 0;   // running minimum and its window
+    uint32_t kmin = kKeyNone;   // the wavefront's smallest key
     int64_t h = (int64_t)pb * (kPairBlock / kWave) + wv;
     // loads of half-tile h: weights, tile, y_j, two float4 of the y_i rows per lane
     float4 w[8], yr0, yr1;
@@ -645,48 +675,35 @@ __device__ void fused_pass_block(const SweepArgs<TX> &a, int pb) {
         if (lane + 64 < nf4) yl[lane + 64] = yr1;
         __builtin_amdgcn_wave_barrier();
         const float *yi0 = reinterpret_cast<const float *>(yl);
-        // the lane's 32 keys go to its row of the LDS key block as they are
-        // produced (nothing stays live across the window computation)
+        // the lane's 32 keys (pair (row0 + e, col0 + lane) in key[e]) stay in
+        // registers, replacing the weights they consume
+        uint32_t key[32];
         uint32_t lmin = kKeyNone;
 #pragma unroll
         for (int g = 0; g < 8; ++g) {
             const float *yi = yi0 + 4 * g * kp;
-            const uint32_t k0 = __float_as_uint(pair_r2<K>(yi, yc, wc[g].x));
-            const uint32_t k1 = __float_as_uint(pair_r2<K>(yi + kp, yc, wc[g].y));
-            const uint32_t k2 = __float_as_uint(pair_r2<K>(yi + 2 * kp, yc, wc[g].z));
-            const uint32_t k3 = __float_as_uint(pair_r2<K>(yi + 3 * kp, yc, wc[g].w));
-            kb4[lane * 9 + g] = make_uint4(k0, k1, k2, k3);
-            lmin = min(lmin, min(min(k0, k1), min(k2, k3)));
+            key[4 * g] = __float_as_uint(pair_r2<K>(yi, yc, wc[g].x));
+            key[4 * g + 1] = __float_as_uint(pair_r2<K>(yi + kp, yc, wc[g].y));
+            key[4 * g + 2] = __float_as_uint(pair_r2<K>(yi + 2 * kp, yc, wc[g].z));
+            key[4 * g + 3] = __float_as_uint(pair_r2<K>(yi + 3 * kp, yc, wc[g].w));
+            lmin = min(lmin, min(min(key[4 * g], key[4 * g + 1]), min(key[4 * g + 2], key[4 * g + 3])));
         }
         const uint32_t m = wave_min_u32_fast(lmin);
-        if (m < kmin) { kmin = m; T2run = item_window(m, a.wa, a.wb); }
-        // the block window is at most the window of the wavefront's running
+        kmin = min(kmin, m);
+        // the block window is at most the window of the block's running
         // minimum: a half-tile whose minimum lies outside it has no candidate
-        if (m <= T2run) {
-            const uint32_t T2 = T2run;
-            uint32_t bits = 0;
-            __builtin_amdgcn_wave_barrier();
-            if (lmin <= T2) {
-#pragma unroll
-                for (int g = 0; g < 8; ++g) {
-                    const uint4 q = kb4[lane * 9 + g];
-                    bits |= ((q.x <= T2 ? 1u : 0u) | (q.y <= T2 ? 2u : 0u) | (q.z <= T2 ? 4u : 0u) |
-                             (q.w <= T2 ? 8u : 0u)) << (4 * g);
-                }
-            }
-            const uint32_t *kb = reinterpret_cast<const uint32_t *>(kb4);
-            append_cands(a, cl, bits, kmin,
-                         [=](int ln, int e) __attribute__((always_inline)) { return kb[ln * 36 + e]; },
-                         [=](int ln, int e, int32_t &i, int32_t &j) __attribute__((always_inline)) {
-                             i = row0 + e;
-                             j = col0 + ln;
-                         },
-                         wb);
-        }
+        const uint32_t T2 = item_window(block_run_min(&s_run, m), a.wa, a.wb);
+        if (m <= T2)
+            emit_cands(cl, key, lmin, T2,
+                       [=](int e, int32_t &i, int32_t &j) __attribute__((always_inline)) {
+                           i = row0 + e;
+                           j = col0 + lane;
+                       },
+                       wb);
         __builtin_amdgcn_wave_barrier();
         if (h + nw < a.nhalf) fetch(h + nw);     // the next half-tile's loads
     }
-    finish_pass_block<K, TX>(a, cl, kmin, wb, a.part + pb);
+    finish_pass_block<K, TX>(a, cl, kmin, &s_run, wb, a.part + pb);
 }
 
 // Plain pass block: one wavefront per 256-pair chunk (grid-stride), the
@@ -696,38 +713,37 @@ __device__ void plain_pass_block(const SweepArgs<TX> &a, int pb) {
     __shared__ int2 s_cij[kPairBlock / kWave][kCandCap];
     __shared__ uint32_t s_ckey[kPairBlock / kWave][kCandCap];
     __shared__ int s_ccnt[kPairBlock / kWave];
+    __shared__ uint32_t s_run;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t wid = (int64_t)pb * (kPairBlock / kWave) + wv;
     const int64_t nw = (int64_t)a.npass * (kPairBlock / kWave);
     WaveBest wb{__builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0};
     CandList cl{s_cij[wv], s_ckey[wv], &s_ccnt[wv], 0, 0};
-    uint32_t kmin = kKeyNone, T2run = 0;   // running minimum and its window
+    uint32_t kmin = kKeyNone;   // the wavefront's smallest key
+    if (threadIdx.x == 0) s_run = kKeyNone;
+    __syncthreads();
     for (int64_t ch = wid; ch < a.nchunks; ch += nw) {
         TX r2[4];
         plain_r2<K, TX>(a.S, a.pcols, a.n, a.Pr, ch * kChunk + lane * 4, r2);
         uint32_t key[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) key[e] = key_of<TX>(r2[e]);
-        const uint32_t m = wave_min_u32_fast(min(min(key[0], key[1]), min(key[2], key[3])));
-        if (m < kmin) { kmin = m; T2run = item_window(m, a.wa, a.wb); }
-        if (m <= T2run) {
-            const uint32_t T2 = T2run;
-            uint32_t bits = 0;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) bits |= (key[e] <= T2 ? 1u : 0u) << e;
-            append_cands(a, cl, bits, kmin,
-                         [&](int ln, int e) { return (uint32_t)__shfl((int)key_at<4>(key, e), ln, kWave); },
-                         [=](int ln, int e, int32_t &i, int32_t &j) __attribute__((always_inline)) {
-                             int64_t ii, jj;
-                             decode_pair(ch * kChunk + ln * 4 + e, a.N, ii, jj);
-                             i = (int32_t)ii;
-                             j = (int32_t)jj;
-                         },
-                         wb);
-        }
+        const uint32_t lmin = min(min(key[0], key[1]), min(key[2], key[3]));
+        const uint32_t m = wave_min_u32_fast(lmin);
+        kmin = min(kmin, m);
+        const uint32_t T2 = item_window(block_run_min(&s_run, m), a.wa, a.wb);
+        if (m <= T2)
+            emit_cands(cl, key, lmin, T2,
+                       [=](int e, int32_t &i, int32_t &j) __attribute__((always_inline)) {
+                           int64_t ii, jj;
+                           decode_pair(ch * kChunk + lane * 4 + e, a.N, ii, jj);
+                           i = (int32_t)ii;
+                           j = (int32_t)jj;
+                       },
+                       wb);
     }
-    finish_pass_block<K, TX>(a, cl, kmin, wb, a.part + pb);
+    finish_pass_block<K, TX>(a, cl, kmin, &s_run, wb, a.part + pb);
 }
 
 // c = P^T (x_i - x_j) for 16 short pairs in FP64 on the matrix cores, tiled
@@ -816,7 +832,7 @@ __device__ void short_block(const SweepArgs<TX> &a, int sb, int nshort) {
 // memory written by other dies' caches).  Returns the winning pair in
 // every thread (i < 0 if there is none).
 template <int K, typename TX, bool FUSED>
-__device__ int2 select_min(const SweepArgs<TX> &a, int nparts) {
+__device__ int2 select_min(const SweepArgs<TX> &a, int nparts, bool record) {
     double best = __builtin_huge_val();
     int32_t bi = 0x7fffffff, bj = 0x7fffffff, nres = 0, nunits = 0, nviol = 0;
     uint32_t kmin = kKeyNone;
@@ -842,7 +858,7 @@ __device__ int2 select_min(const SweepArgs<TX> &a, int nparts) {
     }
     __shared__ Partial s_fin;
     block_reduce_partial(best, bi, bj, nres, nunits, nviol, kmin, &s_fin);
-    if (threadIdx.x == 0) {
+    if (record && threadIdx.x == 0) {
         const Partial f = s_fin;
         double coarse, tr;
         (void)window_key(f.kmin, a.e_abs, a.e_rel, &coarse, &tr);
@@ -877,9 +893,10 @@ __device__ int2 select_min(const SweepArgs<TX> &a, int nparts) {
 // coarse blocks), the other npass blocks score every pair coarsely.  Every
 // block writes its own result slot; the kernel boundary is the grid-wide
 // barrier before selection.
-// (at least three wavefronts per SIMD: the register budget is 168)
+// Occupancy: four wavefronts per SIMD (128 registers) for K <= 7, three
+// (168 registers) above, where 128 would spill.
 template <int K, typename TX, bool FUSED>
-__global__ __launch_bounds__(kPairBlock, 3) void k_pass(SweepArgs<TX> a, int nshort) {
+__global__ __launch_bounds__(kPairBlock, K <= 7 ? 4 : 3) void k_pass(SweepArgs<TX> a, int nshort) {
     if constexpr (FUSED) {
         if ((int)blockIdx.x < nshort) {
             short_block<K, TX>(a, (int)blockIdx.x, nshort);
@@ -1018,7 +1035,7 @@ __device__ __forceinline__ void apply_update(const TX *__restrict__ X, int64_t l
 #pragma unroll
     for (int q = 0; q < K; ++q)
         if (fabs(c[q]) > cmax) { cmax = fabs(c[q]); t = q; }
-    if (tid == 0) res->t = t;
+    if (res && tid == 0) res->t = t;
 
     if (cmax == 0.0) {
         for (int l = tid; l < n; l += kPairBlock) A[l] = s[l];
@@ -1089,15 +1106,18 @@ __device__ __forceinline__ void apply_update(const TX *__restrict__ X, int64_t l
         const double unrm = sqrt(block_sum(un, red, ph));
         for (int l = tid; l < n; l += kPairBlock) A[l] = s[l] / unrm;
     }
-    // write back: master (K x n), row-major FP64 copy, and the plain pass's copy
-    for (int l = tid; l < n; l += kPairBlock) {
+    // write back (each output optional; A itself holds the result): master
+    // (K x n), row-major FP64 copy, and the plain pass's copy
+    if (P64t || P64r || pr_kind) {
+        for (int l = tid; l < n; l += kPairBlock) {
 #pragma unroll
-        for (int q = 0; q < K; ++q) {
-            const double pv = A[(size_t)q * n + l];
-            P64t[(int64_t)q * n + l] = pv;
-            P64r[(int64_t)l * K + q] = pv;
-            if (pr_kind == 1) static_cast<float *>(Pr)[(int64_t)l * K + q] = (float)pv;
-            else if (pr_kind == 2) static_cast<double *>(Pr)[(int64_t)l * K + q] = pv;
+            for (int q = 0; q < K; ++q) {
+                const double pv = A[(size_t)q * n + l];
+                if (P64t) P64t[(int64_t)q * n + l] = pv;
+                if (P64r) P64r[(int64_t)l * K + q] = pv;
+                if (pr_kind == 1) static_cast<float *>(Pr)[(int64_t)l * K + q] = (float)pv;
+                else if (pr_kind == 2) static_cast<double *>(Pr)[(int64_t)l * K + q] = pv;
+            }
         }
     }
 }
@@ -1108,10 +1128,10 @@ __device__ __forceinline__ void apply_update(const TX *__restrict__ X, int64_t l
 // independent inner products of one step (c = P^T s; the projections of all
 // later vectors on q_m) reduced together, so their latencies overlap.
 template <int K, int M, typename TX>
-__device__ __forceinline__ void apply_update_reg(const TX *__restrict__ X, int64_t ldx, int n, const double *Pl,
+__device__ __forceinline__ void apply_update_reg(const TX *__restrict__ X, int64_t ldx, int n, double *Pl,
                                  double *__restrict__ P64t, double *__restrict__ P64r,
                                  void *__restrict__ Pr, int pr_kind, double alpha, int rule,
-                                 DevResult *__restrict__ res, int64_t i, int64_t j) {
+                                 DevResult *__restrict__ res, int64_t i, int64_t j, bool to_lds) {
     const int lane = threadIdx.x & 63;
     double A[K][M], s[M], v[M];
     double d2 = 0.0;
@@ -1142,7 +1162,7 @@ __device__ __forceinline__ void apply_update_reg(const TX *__restrict__ X, int64
 #pragma unroll
     for (int q = 0; q < K; ++q)
         if (fabs(c[q]) > cmax) { cmax = fabs(c[q]); t = q; }
-    if (lane == 0) res->t = t;
+    if (res && lane == 0) res->t = t;
     if (cmax == 0.0) {
 #pragma unroll
         for (int m = 0; m < M; ++m) A[0][m] = s[m];
@@ -1211,6 +1231,8 @@ __device__ __forceinline__ void apply_update_reg(const TX *__restrict__ X, int64
 #pragma unroll
         for (int m = 0; m < M; ++m) A[0][m] = u[m] / unrm;
     }
+    // outputs, each optional: master (K x n), row-major FP64 copy, the plain
+    // pass's copy, and (to_lds) the K x n copy in LDS the update started from
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int l = lane + 64 * m;
@@ -1218,11 +1240,31 @@ __device__ __forceinline__ void apply_update_reg(const TX *__restrict__ X, int64
 #pragma unroll
             for (int q = 0; q < K; ++q) {
                 const double pv = A[q][m];
-                P64t[(int64_t)q * n + l] = pv;
-                P64r[(int64_t)l * K + q] = pv;
+                if (P64t) P64t[(int64_t)q * n + l] = pv;
+                if (P64r) P64r[(int64_t)l * K + q] = pv;
                 if (pr_kind == 1) static_cast<float *>(Pr)[(int64_t)l * K + q] = (float)pv;
                 else if (pr_kind == 2) static_cast<double *>(Pr)[(int64_t)l * K + q] = pv;
+                if (to_lds) Pl[q * n + l] = pv;
             }
+        }
+    }
+}
+
+// The K x n FP64 P into LDS, eight loads in flight per thread before any
+// is stored.
+__device__ __forceinline__ void stage_P(const double *__restrict__ P, int kn, double *sm) {
+#pragma unroll 1
+    for (int e0 = threadIdx.x; e0 < kn; e0 += 8 * kPairBlock) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kPairBlock;
+            t[u] = e < kn ? P[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kPairBlock;
+            if (e < kn) sm[e] = t[u];
         }
     }
 }
@@ -1239,25 +1281,8 @@ __global__ __launch_bounds__(kPairBlock) void k_select(SweepArgs<TX> a, int nsho
     extern __shared__ double sm_dyn[];
     // P into LDS now, so that its loads overlap the selection (the block
     // barriers inside select_min order these writes before the update)
-    // (eight loads in flight per thread before any is stored)
-    if (do_step) {
-        const int kn = K * a.n;
-#pragma unroll 1
-        for (int e0 = threadIdx.x; e0 < kn; e0 += 8 * kPairBlock) {
-            double t[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * kPairBlock;
-                t[u] = e < kn ? a.P64t[e] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * kPairBlock;
-                if (e < kn) sm_dyn[e] = t[u];
-            }
-        }
-    }
-    const int2 ij = select_min<K, TX, FUSED>(a, a.npass + nshort);
+    if (do_step) stage_P(a.P64t, K * a.n, sm_dyn);
+    const int2 ij = select_min<K, TX, FUSED>(a, a.npass + nshort, true);
     if (do_step && ij.x >= 0) {
         // one wavefront with the vectors in registers when every vector
         // fits one 64-lane slice and K is small, the whole block over LDS
@@ -1265,12 +1290,43 @@ __global__ __launch_bounds__(kPairBlock) void k_select(SweepArgs<TX> a, int nsho
         if (K <= 8 && a.n <= 64) {
             if (threadIdx.x < kWave)
                 apply_update_reg<K, 1, TX>(a.X, a.ldx, a.n, sm_dyn, P64t, P64r, Pr, pr_kind, alpha, rule,
-                                           a.res, ij.x, ij.y);
+                                           a.res, ij.x, ij.y, false);
         } else {
             apply_update<K, TX>(a.X, a.ldx, a.n, P64t, P64r, Pr, pr_kind, alpha, rule, a.res, ij.x,
                                 ij.y, sm_dyn);
         }
     }
+}
+
+// Fused form inside a run: this iteration's selection and update (as
+// k_select) followed by the next iteration's Y = (X - mu) P' (as k_prep), in
+// every block of the GEMM's grid, so the run needs two launches per
+// iteration.  Every block takes the same selection and computes the same P'
+// (identical inputs, identical arithmetic) into its LDS, then its rows of Y
+// from there.  Block 0 alone writes the record, the traces and P' to Pn, the
+// other P buffer: blocks still reading the current P must not see P'.
+template <int K, typename TX>
+__global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nshort, double *__restrict__ Pn,
+                                                        double alpha, int rule, const double *__restrict__ mu,
+                                                        float *__restrict__ Y, int64_t Npad) {
+    extern __shared__ __align__(16) double sm_sp[];
+    const bool lead = blockIdx.x == 0;
+    stage_P(a.P64t, K * a.n, sm_sp);
+    const int2 ij = select_min<K, TX, true>(a, a.npass + nshort, lead);
+    if (ij.x >= 0) {
+        if (K <= 8 && a.n <= 64) {
+            if (threadIdx.x < kWave)
+                apply_update_reg<K, 1, TX>(a.X, a.ldx, a.n, sm_sp, lead ? Pn : nullptr, nullptr, nullptr, 0,
+                                           alpha, rule, lead ? a.res : nullptr, ij.x, ij.y, true);
+        } else {
+            apply_update<K, TX>(a.X, a.ldx, a.n, lead ? Pn : nullptr, nullptr, nullptr, 0, alpha, rule,
+                                lead ? a.res : nullptr, ij.x, ij.y, sm_sp);
+        }
+    } else if (lead) {
+        for (int e = threadIdx.x; e < K * a.n; e += kPairBlock) Pn[e] = sm_sp[e];   // P unchanged
+    }
+    __syncthreads();
+    gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, sm_sp, Y, a.kp, Npad, a.vx, (a.n & 1) == 0);
 }
 
 // ------------------------------------------------------------------ small helpers

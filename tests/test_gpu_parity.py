@@ -145,6 +145,39 @@ def test_set_get_P_roundtrip_and_resume():
     ctx.close()
 
 
+@pytest.mark.parametrize("name,N,k", [("trig64", 300, 6), ("hyper", 300, 10), ("blob", 200, 8)])
+def test_fused_run_equals_steps(name, N, k):
+    """sap_run in the fused form fuses each iteration's selection and update
+    with the next iteration's Y GEMM (two P buffers).  It must give exactly
+    what separate sap_step calls and a final sap_min_secant give: the same
+    trace and the same final basis, bit for bit.  The cases cover the
+    register update (n <= 64, k <= 8) and the block-wide LDS update."""
+    w = sap_inputs.make(name, N=N, k=k)
+    iters = 6
+    ctx_r, _ = _ctx(w, "fused")
+    tr = ctx_r.run(iters)
+    torch.cuda.synchronize()
+    P_run = ctx_r.get_P().cpu().numpy()
+    ctx_s, _ = _ctx(w, "fused")
+    steps = [ctx_s.step(sync=True) for _ in range(iters)]
+    steps.append(ctx_s.min_secant())
+    P_step = ctx_s.get_P().cpu().numpy()
+    gmin = tr["min"].cpu().numpy()
+    gij = tr["ij"].cpu().numpy()
+    for it, r in enumerate(steps):
+        assert (int(gij[it][0]), int(gij[it][1])) == (r["i"], r["j"]), (it, gij[it], r)
+        assert gmin[it] == r["min_norm"], (it, gmin[it], r["min_norm"])
+    assert np.array_equal(P_run, P_step)
+    # the run resumes from its final basis: a second run continues the trajectory
+    tr2 = ctx_r.run(2)
+    torch.cuda.synchronize()
+    ctx_s.step(sync=True)
+    ctx_s.step(sync=True)
+    assert np.array_equal(ctx_r.get_P().cpu().numpy(), ctx_s.get_P().cpu().numpy())
+    assert float(tr2["min"][0].item()) == gmin[iters]
+    ctx_r.close(); ctx_s.close()
+
+
 # ------------------------------------------------------------------ edge cases
 
 def test_two_points():
