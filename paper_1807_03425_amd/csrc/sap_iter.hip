@@ -128,10 +128,22 @@ __device__ __forceinline__ void load16(const double *__restrict__ p, bool vec, d
 // l0 + 16 kk + s, so each lane reads 16 consecutive components of its row
 // (and of P's column): 16-byte loads when vx (X rows 16-byte aligned) and vp
 // (n even).  Every operand load of a chunk is issued before its 16 MFMAs.
+// The lane's X row of gemm_block: its first chunk's 16 values (n >= 64).
+template <typename TX>
+__device__ __forceinline__ void gemm_first_x(const TX *__restrict__ X, int64_t ldx, int64_t N, int64_t Npad,
+                                             bool vx, double (&xa)[16]) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row0 = min(((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16, Npad - 16);
+    const int64_t row = row0 + (lane & 15);
+    load16(X + (row < N ? row : N - 1) * ldx + 16 * (lane >> 4), vx, xa);
+}
+
+// x0 (optional): the first chunk's X values, loaded earlier by gemm_first_x.
 template <typename TX>
 __device__ void gemm_block(const TX *__restrict__ X, int64_t ldx, int64_t N, int n, int k,
                            const double *__restrict__ mu, const double *__restrict__ P64t,
-                           float *__restrict__ Y, int kp, int64_t Npad, bool vx, bool vp) {
+                           float *__restrict__ Y, int kp, int64_t Npad, bool vx, bool vp,
+                           const double *x0 = nullptr) {
     const int lane = threadIdx.x & 63;
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
     if (row0 >= Npad) return;
@@ -149,7 +161,12 @@ __device__ void gemm_block(const TX *__restrict__ X, int64_t ldx, int64_t N, int
     for (; l0 + 64 <= n; l0 += 64) {
         double xa[16], ma[16], pb[16];
         const int lb = l0 + 16 * kk;
-        load16(xr + lb, vx, xa);
+        if (x0 && l0 == 0) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) xa[u] = x0[u];
+        } else {
+            load16(xr + lb, vx, xa);
+        }
         load16(mu + lb, true, ma);
         load16(pc + lb, vp, pb);
 #pragma unroll
@@ -580,8 +597,8 @@ __device__ __forceinline__ uint32_t block_run_min(uint32_t *s_run, uint32_t m) {
 
 // After the pass loop: keep the candidates with key <= T2b, rescore them.
 template <int K, typename TX>
-__device__ __forceinline__ void rescore_cands(const SweepArgs<TX> &a, const CandList &cl,
-                                              uint32_t T2b, WaveBest &wb) {
+__device__ __forceinline__ void rescore_cands(const SweepArgs<TX> &a, const CandList &cl, uint32_t T2b,
+                                              WaveBest &wb) {
     __builtin_amdgcn_wave_barrier();
 #pragma unroll 1
     for (int c = 0; c < cl.n; ++c) {
@@ -593,7 +610,6 @@ __device__ __forceinline__ void rescore_cands(const SweepArgs<TX> &a, const Cand
         wb.nviol += bound_broken(r, (double)__uint_as_float(kv), a.e_abs, a.e_rel);
         if (lex_less(r, ij.x, ij.y, wb.r, wb.i, wb.j)) { wb.r = r; wb.i = ij.x; wb.j = ij.y; }
     }
-    wb.nviol += cl.lost;   // dropped candidates: the result is not certified
 }
 
 // Block minimum of the wavefronts' coarse minima (uniform per wavefront),
@@ -609,6 +625,7 @@ __device__ __forceinline__ void finish_pass_block(const SweepArgs<TX> &a, const 
     // other wavefronts
     const uint32_t run = __builtin_amdgcn_readfirstlane(*(const volatile uint32_t *)s_run);
     if (run < 0x7f800000u) rescore_cands<K, TX>(a, cl, item_window(run, a.wa, a.wb), wb);
+    wb.nviol += cl.lost;   // dropped candidates: the result is not certified
     const int lane = threadIdx.x & 63;
     block_reduce_partial(wb.r, wb.i, wb.j, lane == 0 ? wb.nwin : 0, lane == 0 ? wb.nunits : 0,
                          lane == 0 ? wb.nviol : 0, kmin, out);
@@ -1311,8 +1328,30 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
                                                         float *__restrict__ Y, int64_t Npad) {
     extern __shared__ __align__(16) double sm_sp[];
     const bool lead = blockIdx.x == 0;
-    stage_P(a.P64t, K * a.n, sm_sp);
+    // small P: its loads are issued first and land in registers while the
+    // selection's loads are in flight (one wait covers both); it goes to
+    // LDS after the selection, before the barrier the update starts behind
+    const int kn = K * a.n;
+    const bool small = kn <= 8 * kPairBlock;
+    // the GEMM's first chunk of X is loaded now too, out of the critical path
+    double x0[16];
+    if (a.n >= 64) gemm_first_x<TX>(a.X, a.ldx, a.N, Npad, a.vx, x0);
+    double pre[8];
+    if (small) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pre[u] = a.P64t[min((int)threadIdx.x + u * kPairBlock, kn - 1)];
+    } else {
+        stage_P(a.P64t, kn, sm_sp);
+    }
     const int2 ij = select_min<K, TX, true>(a, a.npass + nshort, lead);
+    if (small) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = (int)threadIdx.x + u * kPairBlock;
+            if (e < kn) sm_sp[e] = pre[u];
+        }
+        __syncthreads();
+    }
     if (ij.x >= 0) {
         if (K <= 8 && a.n <= 64) {
             if (threadIdx.x < kWave)
@@ -1326,7 +1365,8 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
         for (int e = threadIdx.x; e < K * a.n; e += kPairBlock) Pn[e] = sm_sp[e];   // P unchanged
     }
     __syncthreads();
-    gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, sm_sp, Y, a.kp, Npad, a.vx, (a.n & 1) == 0);
+    gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, sm_sp, Y, a.kp, Npad, a.vx, (a.n & 1) == 0,
+                   a.n >= 64 ? x0 : nullptr);
 }
 
 // ------------------------------------------------------------------ small helpers
