@@ -656,48 +656,54 @@ __device__ void fused_pass_block(const SweepArgs<TX> &a, int pb) {
     float4 *yl = s_y[wv];
     if (threadIdx.x == 0) s_run = kKeyNone;
     __syncthreads();
-    const int nf4 = 8 * kp;                  // float4 count of 32 rows of Y (<= 128)
+    // work item: G groups of 4 rows against the tile's 64 columns (a
+    // half-tile; a quarter-tile for K >= 8, which halves the registers the
+    // item holds so that the pass keeps four wavefronts per SIMD)
+    constexpr int G = K <= 7 ? 8 : 4;
+    constexpr int IPT = 16 / G;              // items per tile
+    const int64_t nitem = a.nhalf * (8 / G);
+    const int nf4 = G * kp;                  // float4 count of the item's 4G rows of Y (<= 128)
     WaveBest wb{__builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0};
     CandList cl{s_cij[wv], s_ckey[wv], &s_ccnt[wv], 0, 0};
     uint32_t kmin = kKeyNone;   // the wavefront's smallest key
     int64_t h = (int64_t)pb * (kPairBlock / kWave) + wv;
-    // loads of half-tile h: weights, tile, y_j, two float4 of the y_i rows per lane
-    float4 w[8], yr0, yr1;
+    // loads of item h: weights, tile, y_j, two float4 of the y_i rows per lane
+    float4 w[G], yr0, yr1;
     float yj[K];
     int2 bt;
     auto fetch = [&](int64_t hh) __attribute__((always_inline)) {
-        const int64_t t = hh >> 1;
-        const int half = (int)(hh & 1);
-        const float4 *tp = a.invd2 + t * (kTileElems / 4) + half * 512 + lane;
+        const int64_t t = hh / IPT;
+        const int part = (int)(hh % IPT);
+        const float4 *tp = a.invd2 + t * (kTileElems / 4) + part * (G * 64) + lane;
 #pragma unroll
-        for (int g = 0; g < 8; ++g) w[g] = tp[g * 64];
+        for (int g = 0; g < G; ++g) w[g] = tp[g * 64];
         bt = a.tiles[t];
         const float4 *ysrc =
-            reinterpret_cast<const float4 *>(a.Y + ((int64_t)bt.x * kTile + 32 * half) * kp);
+            reinterpret_cast<const float4 *>(a.Y + ((int64_t)bt.x * kTile + 4 * G * part) * kp);
         yr0 = ysrc[lane < nf4 ? lane : 0];
         yr1 = ysrc[lane + 64 < nf4 ? lane + 64 : 0];
         load_yj<K>(a.Y, kp, (int64_t)bt.y * kTile + lane, yj);
     };
-    if (h < a.nhalf) fetch(h);
-    for (; h < a.nhalf; h += nw) {
-        float4 wc[8];
+    if (h < nitem) fetch(h);
+    for (; h < nitem; h += nw) {
+        float4 wc[G];
 #pragma unroll
-        for (int g = 0; g < 8; ++g) wc[g] = w[g];
+        for (int g = 0; g < G; ++g) wc[g] = w[g];
         float yc[K];
 #pragma unroll
         for (int c = 0; c < K; ++c) yc[c] = yj[c];
-        const int32_t row0 = bt.x * kTile + 32 * (int32_t)(h & 1), col0 = bt.y * kTile;
+        const int32_t row0 = bt.x * kTile + 4 * G * (int32_t)(h % IPT), col0 = bt.y * kTile;
         __builtin_amdgcn_wave_barrier();
         if (lane < nf4) yl[lane] = yr0;
         if (lane + 64 < nf4) yl[lane + 64] = yr1;
         __builtin_amdgcn_wave_barrier();
         const float *yi0 = reinterpret_cast<const float *>(yl);
-        // the lane's 32 keys (pair (row0 + e, col0 + lane) in key[e]) stay in
+        // the lane's 4G keys (pair (row0 + e, col0 + lane) in key[e]) stay in
         // registers, replacing the weights they consume
-        uint32_t key[32];
+        uint32_t key[4 * G];
         uint32_t lmin = kKeyNone;
 #pragma unroll
-        for (int g = 0; g < 8; ++g) {
+        for (int g = 0; g < G; ++g) {
             const float *yi = yi0 + 4 * g * kp;
             key[4 * g] = __float_as_uint(pair_r2<K>(yi, yc, wc[g].x));
             key[4 * g + 1] = __float_as_uint(pair_r2<K>(yi + kp, yc, wc[g].y));
@@ -718,7 +724,7 @@ __device__ void fused_pass_block(const SweepArgs<TX> &a, int pb) {
                        },
                        wb);
         __builtin_amdgcn_wave_barrier();
-        if (h + nw < a.nhalf) fetch(h + nw);     // the next half-tile's loads
+        if (h + nw < nitem) fetch(h + nw);       // the next item's loads
     }
     finish_pass_block<K, TX>(a, cl, kmin, &s_run, wb, a.part + pb);
 }
@@ -910,10 +916,10 @@ __device__ int2 select_min(const SweepArgs<TX> &a, int nparts, bool record) {
 // coarse blocks), the other npass blocks score every pair coarsely.  Every
 // block writes its own result slot; the kernel boundary is the grid-wide
 // barrier before selection.
-// Occupancy: four wavefronts per SIMD (128 registers) for K <= 7, three
-// (168 registers) above, where 128 would spill.
+// Occupancy: four wavefronts per SIMD (128 registers); three (168) for the
+// plain form over FP64 data with K > 12, which would spill at 128.
 template <int K, typename TX, bool FUSED>
-__global__ __launch_bounds__(kPairBlock, K <= 7 ? 4 : 3) void k_pass(SweepArgs<TX> a, int nshort) {
+__global__ __launch_bounds__(kPairBlock, (FUSED || sizeof(TX) == 4 || K <= 12) ? 4 : 3) void k_pass(SweepArgs<TX> a, int nshort) {
     if constexpr (FUSED) {
         if ((int)blockIdx.x < nshort) {
             short_block<K, TX>(a, (int)blockIdx.x, nshort);
