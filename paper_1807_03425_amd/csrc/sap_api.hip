@@ -74,7 +74,6 @@ struct sap_ctx {
     // common
     double *d_P64t = nullptr;       // the current P (FP64 master, K x n)
     double *d_P64t_alt = nullptr;   // fused: the other P buffer, written by k_selprep
-    double *d_P64r = nullptr;
     double *d_mu = nullptr;
     DevState *d_st = nullptr;
     Partial *d_part = nullptr;   // pass-block results, then one per short-pair block
@@ -227,16 +226,15 @@ static sap_status load_P(sap_ctx *h, const double *P_dev) {
         for (int q = 0; q < k; ++q) Pt[(size_t)q * n + l] = P[(size_t)l * k + q];
     SAP_HIP(h, hipMemcpyAsync(h->d_P64t, Pt.data(), sizeof(double) * n * k, hipMemcpyHostToDevice,
                               h->stream));
-    {
+    if (h->cfg.form == SAP_PLAIN) {
         const int blocks = (int)ceil_div((int64_t)n * k, 256);
-        if (h->cfg.form == SAP_PLAIN && h->cfg.dtype == SAP_F64)
-            hipLaunchKernelGGL(k_write_P_copies<double>, dim3(blocks), dim3(256), 0, h->stream,
-                               h->d_P64t, n, k, h->d_P64r, static_cast<double *>(h->d_Pr));
+        if (h->cfg.dtype == SAP_F64)
+            hipLaunchKernelGGL(k_write_Pr<double>, dim3(blocks), dim3(256), 0, h->stream, h->d_P64t, n, k,
+                               static_cast<double *>(h->d_Pr));
         else
-            hipLaunchKernelGGL(k_write_P_copies<float>, dim3(blocks), dim3(256), 0, h->stream,
-                               h->d_P64t, n, k, h->d_P64r,
-                               h->cfg.form == SAP_PLAIN ? static_cast<float *>(h->d_Pr) : nullptr);
-        SAP_LAUNCHED(h, "k_write_P_copies");
+            hipLaunchKernelGGL(k_write_Pr<float>, dim3(blocks), dim3(256), 0, h->stream, h->d_P64t, n, k,
+                               static_cast<float *>(h->d_Pr));
+        SAP_LAUNCHED(h, "k_write_Pr");
     }
     SAP_HIP(h, hipStreamSynchronize(h->stream));
     return SAP_OK;
@@ -536,11 +534,11 @@ static sap_status launch_select(sap_ctx *h, int do_step, double *tr_min, int64_t
     const dim3 blk(kPairBlock);
     if (fused) {
         SAP_DISPATCH_K(K, SAP_TRY(launch(h, 2, "k_select", k_select<K, TX, true>, dim3(1), blk, lds,
-                                         a, nshort, h->d_P64t, h->d_P64r, h->d_Pr, pr_kind,
+                                         a, nshort, h->d_P64t, h->d_Pr, pr_kind,
                                          h->cfg.alpha, h->cfg.rule, do_step)));
     } else {
         SAP_DISPATCH_K(K, SAP_TRY(launch(h, 2, "k_select", k_select<K, TX, false>, dim3(1), blk, lds,
-                                         a, nshort, h->d_P64t, h->d_P64r, h->d_Pr, pr_kind,
+                                         a, nshort, h->d_P64t, h->d_Pr, pr_kind,
                                          h->cfg.alpha, h->cfg.rule, do_step)));
     }
     return SAP_OK;
@@ -759,7 +757,6 @@ sap_status sap_init(const sap_config *cfg, const void *X, int64_t ldx, const dou
     if (e != hipSuccess) return bail(fail(h, SAP_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
     sap_status s;
     if ((s = dalloc(h, &h->d_P64t, sizeof(double) * h->n * h->k)) != SAP_OK) return bail(s);
-    if ((s = dalloc(h, &h->d_P64r, sizeof(double) * h->n * h->k)) != SAP_OK) return bail(s);
     if ((s = dalloc(h, &h->d_mu, sizeof(double) * h->n)) != SAP_OK) return bail(s);
     if ((s = dalloc(h, &h->d_st, sizeof(DevState))) != SAP_OK) return bail(s);
     if ((s = dalloc(h, &h->d_res, sizeof(DevResult))) != SAP_OK) return bail(s);

@@ -1026,9 +1026,9 @@ __device__ __forceinline__ double block_sum(double x, double (*red)[kPairBlock /
 // (|a_m| and the batch).  Every thread of the block must call this.
 template <int K, typename TX>
 __device__ __forceinline__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
-                             double *__restrict__ P64t, double *__restrict__ P64r,
-                             void *__restrict__ Pr, int pr_kind, double alpha, int rule,
-                             DevResult *__restrict__ res, int64_t i, int64_t j, double *sm) {
+                             double *__restrict__ P64t, void *__restrict__ Pr, int pr_kind,
+                             double alpha, int rule, DevResult *__restrict__ res, int64_t i, int64_t j,
+                             double *sm) {
     __shared__ double red[2][kPairBlock / kWave][16];
     int ph = 0;
     const int tid = threadIdx.x;
@@ -1130,14 +1130,13 @@ __device__ __forceinline__ void apply_update(const TX *__restrict__ X, int64_t l
         for (int l = tid; l < n; l += kPairBlock) A[l] = s[l] / unrm;
     }
     // write back (each output optional; A itself holds the result): master
-    // (K x n), row-major FP64 copy, and the plain pass's copy
-    if (P64t || P64r || pr_kind) {
+    // (K x n) and the plain pass's copy
+    if (P64t || pr_kind) {
         for (int l = tid; l < n; l += kPairBlock) {
 #pragma unroll
             for (int q = 0; q < K; ++q) {
                 const double pv = A[(size_t)q * n + l];
                 if (P64t) P64t[(int64_t)q * n + l] = pv;
-                if (P64r) P64r[(int64_t)l * K + q] = pv;
                 if (pr_kind == 1) static_cast<float *>(Pr)[(int64_t)l * K + q] = (float)pv;
                 else if (pr_kind == 2) static_cast<double *>(Pr)[(int64_t)l * K + q] = pv;
             }
@@ -1152,9 +1151,9 @@ __device__ __forceinline__ void apply_update(const TX *__restrict__ X, int64_t l
 // later vectors on q_m) reduced together, so their latencies overlap.
 template <int K, int M, typename TX>
 __device__ __forceinline__ void apply_update_reg(const TX *__restrict__ X, int64_t ldx, int n, double *Pl,
-                                 double *__restrict__ P64t, double *__restrict__ P64r,
-                                 void *__restrict__ Pr, int pr_kind, double alpha, int rule,
-                                 DevResult *__restrict__ res, int64_t i, int64_t j, bool to_lds) {
+                                 double *__restrict__ P64t, void *__restrict__ Pr, int pr_kind,
+                                 double alpha, int rule, DevResult *__restrict__ res, int64_t i,
+                                 int64_t j, bool to_lds) {
     const int lane = threadIdx.x & 63;
     double A[K][M], s[M], v[M];
     double d2 = 0.0;
@@ -1254,8 +1253,8 @@ __device__ __forceinline__ void apply_update_reg(const TX *__restrict__ X, int64
 #pragma unroll
         for (int m = 0; m < M; ++m) A[0][m] = u[m] / unrm;
     }
-    // outputs, each optional: master (K x n), row-major FP64 copy, the plain
-    // pass's copy, and (to_lds) the K x n copy in LDS the update started from
+    // outputs, each optional: master (K x n), the plain pass's copy, and
+    // (to_lds) the K x n copy in LDS the update started from
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int l = lane + 64 * m;
@@ -1264,7 +1263,6 @@ __device__ __forceinline__ void apply_update_reg(const TX *__restrict__ X, int64
             for (int q = 0; q < K; ++q) {
                 const double pv = A[q][m];
                 if (P64t) P64t[(int64_t)q * n + l] = pv;
-                if (P64r) P64r[(int64_t)l * K + q] = pv;
                 if (pr_kind == 1) static_cast<float *>(Pr)[(int64_t)l * K + q] = (float)pv;
                 else if (pr_kind == 2) static_cast<double *>(Pr)[(int64_t)l * K + q] = pv;
                 if (to_lds) Pl[q * n + l] = pv;
@@ -1298,7 +1296,6 @@ __device__ __forceinline__ void stage_P(const double *__restrict__ P, int kn, do
 template <int K, typename TX, bool FUSED>
 __global__ __launch_bounds__(kPairBlock) void k_select(SweepArgs<TX> a, int nshort,
                                                        double *__restrict__ P64t,
-                                                       double *__restrict__ P64r,
                                                        void *__restrict__ Pr, int pr_kind,
                                                        double alpha, int rule, int do_step) {
     extern __shared__ double sm_dyn[];
@@ -1312,10 +1309,10 @@ __global__ __launch_bounds__(kPairBlock) void k_select(SweepArgs<TX> a, int nsho
         // otherwise
         if (K <= 8 && a.n <= 64) {
             if (threadIdx.x < kWave)
-                apply_update_reg<K, 1, TX>(a.X, a.ldx, a.n, sm_dyn, P64t, P64r, Pr, pr_kind, alpha, rule,
+                apply_update_reg<K, 1, TX>(a.X, a.ldx, a.n, sm_dyn, P64t, Pr, pr_kind, alpha, rule,
                                            a.res, ij.x, ij.y, false);
         } else {
-            apply_update<K, TX>(a.X, a.ldx, a.n, P64t, P64r, Pr, pr_kind, alpha, rule, a.res, ij.x,
+            apply_update<K, TX>(a.X, a.ldx, a.n, P64t, Pr, pr_kind, alpha, rule, a.res, ij.x,
                                 ij.y, sm_dyn);
         }
     }
@@ -1361,10 +1358,10 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
     if (ij.x >= 0) {
         if (K <= 8 && a.n <= 64) {
             if (threadIdx.x < kWave)
-                apply_update_reg<K, 1, TX>(a.X, a.ldx, a.n, sm_sp, lead ? Pn : nullptr, nullptr, nullptr, 0,
-                                           alpha, rule, lead ? a.res : nullptr, ij.x, ij.y, true);
+                apply_update_reg<K, 1, TX>(a.X, a.ldx, a.n, sm_sp, lead ? Pn : nullptr, nullptr, 0, alpha,
+                                           rule, lead ? a.res : nullptr, ij.x, ij.y, true);
         } else {
-            apply_update<K, TX>(a.X, a.ldx, a.n, lead ? Pn : nullptr, nullptr, nullptr, 0, alpha, rule,
+            apply_update<K, TX>(a.X, a.ldx, a.n, lead ? Pn : nullptr, nullptr, 0, alpha, rule,
                                 lead ? a.res : nullptr, ij.x, ij.y, sm_sp);
         }
     } else if (lead) {
@@ -1377,16 +1374,13 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
 
 // ------------------------------------------------------------------ small helpers
 
-// Write the row-major copies of P (FP64, and the plain pass's T) from the master.
+// The plain pass's n x k row-major copy of P in X's dtype, from the master.
 template <typename T>
-__global__ void k_write_P_copies(const double *__restrict__ P64t, int n, int k,
-                                 double *__restrict__ P64r, T *__restrict__ Pr) {
+__global__ void k_write_Pr(const double *__restrict__ P64t, int n, int k, T *__restrict__ Pr) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * k) return;
     const int l = e / k, q = e % k;
-    const double pv = P64t[(int64_t)q * n + l];
-    P64r[e] = pv;
-    if (Pr) Pr[e] = (T)pv;
+    Pr[e] = (T)P64t[(int64_t)q * n + l];
 }
 
 // P_out (n x k row-major) <- master (k x n)
