@@ -237,10 +237,13 @@ __global__ __launch_bounds__(kPairBlock) void k_sm_fin(const SmPart *__restrict_
 // stride 65: conflict-free both ways).  Phase 2 (lane = row i = lane % 32,
 // column half lane / 32): z_i += a_ij (y_i - y_j) over its 32 columns, then the
 // two halves are added.  Partials go to Zr / Zc, component-major per half-tile.
+// LDS sized for K's padded row length, and at most 168 registers: three
+// blocks (three wavefronts per SIMD) fit a compute unit.
 template <int K>
-__global__ __launch_bounds__(kPairBlock) void k_sm_bwd(SmArgs a) {
-    __shared__ float4 s_y[kPairBlock / kWave][32 * kMaxK / 4];
-    __shared__ float4 s_yc[kPairBlock / kWave][64 * kMaxK / 4];
+__global__ __launch_bounds__(kPairBlock, 3) void k_sm_bwd(SmArgs a) {
+    constexpr int KP = K <= 4 ? 4 : (K <= 8 ? 8 : (K <= 12 ? 12 : 16));   // the Y row length kp
+    __shared__ float4 s_y[kPairBlock / kWave][32 * KP / 4];
+    __shared__ float4 s_yc[kPairBlock / kWave][64 * KP / 4];
     __shared__ float s_a[kPairBlock / kWave][32 * 65];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
