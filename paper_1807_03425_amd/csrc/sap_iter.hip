@@ -128,22 +128,26 @@ __device__ __forceinline__ void load16(const double *__restrict__ p, bool vec, d
 // l0 + 16 kk + s, so each lane reads 16 consecutive components of its row
 // (and of P's column): 16-byte loads when vx (X rows 16-byte aligned) and vp
 // (n even).  Every operand load of a chunk is issued before its 16 MFMAs.
-// The lane's X row of gemm_block: its first chunk's 16 values (n >= 64).
+// The lane's operands of gemm_block's first chunk (n >= 64): 16 values of
+// its X row and the matching 16 column means.
 template <typename TX>
 __device__ __forceinline__ void gemm_first_x(const TX *__restrict__ X, int64_t ldx, int64_t N, int64_t Npad,
-                                             bool vx, double (&xa)[16]) {
+                                             bool vx, const double *__restrict__ mu, double (&xa)[16],
+                                             double (&ma)[16]) {
     const int lane = threadIdx.x & 63;
     const int64_t row0 = min(((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16, Npad - 16);
     const int64_t row = row0 + (lane & 15);
     load16(X + (row < N ? row : N - 1) * ldx + 16 * (lane >> 4), vx, xa);
+    load16(mu + 16 * (lane >> 4), true, ma);
 }
 
-// x0 (optional): the first chunk's X values, loaded earlier by gemm_first_x.
+// x0, m0 (optional): the first chunk's X values and means, loaded earlier
+// by gemm_first_x.
 template <typename TX>
 __device__ void gemm_block(const TX *__restrict__ X, int64_t ldx, int64_t N, int n, int k,
                            const double *__restrict__ mu, const double *__restrict__ P64t,
                            float *__restrict__ Y, int kp, int64_t Npad, bool vx, bool vp,
-                           const double *x0 = nullptr) {
+                           const double *x0 = nullptr, const double *m0 = nullptr) {
     const int lane = threadIdx.x & 63;
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
     if (row0 >= Npad) return;
@@ -163,11 +167,11 @@ __device__ void gemm_block(const TX *__restrict__ X, int64_t ldx, int64_t N, int
         const int lb = l0 + 16 * kk;
         if (x0 && l0 == 0) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) xa[u] = x0[u];
+            for (int u = 0; u < 16; ++u) { xa[u] = x0[u]; ma[u] = m0[u]; }
         } else {
             load16(xr + lb, vx, xa);
+            load16(mu + lb, true, ma);
         }
-        load16(mu + lb, true, ma);
         load16(pc + lb, vp, pb);
 #pragma unroll
         for (int s = 0; s < 16; ++s)
@@ -1336,9 +1340,10 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
     // LDS after the selection, before the barrier the update starts behind
     const int kn = K * a.n;
     const bool small = kn <= 8 * kPairBlock;
-    // the GEMM's first chunk of X is loaded now too, out of the critical path
-    double x0[16];
-    if (a.n >= 64) gemm_first_x<TX>(a.X, a.ldx, a.N, Npad, a.vx, x0);
+    // the GEMM's first chunk of X and of the means are loaded now too, out of
+    // the critical path
+    double x0[16], m0[16];
+    if (a.n >= 64) gemm_first_x<TX>(a.X, a.ldx, a.N, Npad, a.vx, mu, x0, m0);
     double pre[8];
     if (small) {
 #pragma unroll
@@ -1369,7 +1374,7 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
     }
     __syncthreads();
     gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, sm_sp, Y, a.kp, Npad, a.vx, (a.n & 1) == 0,
-                   a.n >= 64 ? x0 : nullptr);
+                   a.n >= 64 ? x0 : nullptr, m0);
 }
 
 // ------------------------------------------------------------------ small helpers
