@@ -424,8 +424,8 @@ static sap_status init_fused(sap_ctx *h) {
     h->close_d = dtarget * std::pow(2.0, -msel / 4.0);
     h->e_abs = st.keep_max ? 2.0 * delta * std::sqrt((double)wmax * (1.0 + std::ldexp(1.0, -22))) : 0.0;
     h->e_rel = (h->k + 4) * kU32;
-    // at least two half-tiles per wavefront (the next one's loads overlap the
-    // current one's arithmetic), four wavefronts per block
+    // SAP_HALVES_PER_BLOCK half-tiles per block of four wavefronts (the
+    // blocks stride over the rest when the grid is capped)
     h->pass_grid = (int)std::min<int64_t>(ceil_div(2 * h->ntiles, SAP_HALVES_PER_BLOCK), 8192);
     // iteration: 64 short pairs per block (16 per wavefront, on the matrix
     // cores); the soft-min's short-pair blocks use the same grid size

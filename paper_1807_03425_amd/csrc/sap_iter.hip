@@ -635,17 +635,18 @@ __device__ __forceinline__ void finish_pass_block(const SweepArgs<TX> &a, const 
                          lane == 0 ? wb.nviol : 0, kmin, out);
 }
 
-// Fused pass block pb.  Wavefront w = 4 pb + slot takes half-tiles
-// h = w, w + nw, ... (h = 2 t + half: rows 64 bi + 32 half .. +31 against the
-// 64 columns of tile t = (bi, bj)).  Every load of a half-tile (8 weight
-// float4 per lane, the lane's y_j, its share of the 32 y_i rows) is issued
-// at once, before any is used; the y_i rows go through the wavefront's own
-// LDS slice (read back as broadcasts; no other wavefront touches it, so no
-// block barrier).
-// Per pair: K subtractions, K FMAs, one multiply, one unsigned min.  Only a
-// half-tile whose minimum lies inside the window of the block's running
-// minimum is scanned for candidates (emit_cands); they are rescored after the
-// loop (finish_pass_block).
+// Fused pass block pb.  Wavefront w = 4 pb + slot takes work items
+// h = w, w + nw, ...: item h covers 4G rows of tile t = h / IPT = (bi, bj)
+// (rows 64 bi + 4G (h % IPT) ..) against its 64 columns; G = 8 (a half-tile),
+// or 4 for K >= 8.  An item's loads (G weight float4 per lane, the lane's y_j,
+// its share of the item's y_i rows) are issued together once the tile's
+// coordinates are in, at the end of the previous item; the y_i rows go
+// through the wavefront's own LDS slice (read back as broadcasts; no other
+// wavefront touches it, so no block barrier).
+// Per pair: K subtractions, K FMAs, one multiply, one unsigned min.  Only an
+// item whose minimum lies inside the window of the block's running minimum
+// is scanned for candidates (emit_cands); they are rescored after the loop
+// (finish_pass_block).
 template <int K, typename TX>
 __device__ void fused_pass_block(const SweepArgs<TX> &a, int pb) {
     __shared__ float4 s_y[kPairBlock / kWave][32 * kMaxK / 4];
