@@ -571,16 +571,27 @@ __device__ __forceinline__ void emit_cands(CandList &cl, const uint32_t (&key)[N
     }
     if (bits) {
         int pos = cl.n + base;
+        if ((bits & (bits - 1u)) == 0u) {
+            // one key in the window: it is the lane's smallest (the usual
+            // case, a new running minimum)
+            if (pos < kCandCap) {
+                int32_t i, j;
+                pair(__builtin_ctz(bits), i, j);
+                cl.ij[pos] = make_int2(i, j);
+                cl.key[pos] = lmin;
+            }
+        } else {
 #pragma unroll
-        for (int e = 0; e < NK; ++e) {
-            if ((bits >> e) & 1u) {
-                if (pos < kCandCap) {
-                    int32_t i, j;
-                    pair(e, i, j);
-                    cl.ij[pos] = make_int2(i, j);
-                    cl.key[pos] = key[e];
+            for (int e = 0; e < NK; ++e) {
+                if ((bits >> e) & 1u) {
+                    if (pos < kCandCap) {
+                        int32_t i, j;
+                        pair(e, i, j);
+                        cl.ij[pos] = make_int2(i, j);
+                        cl.key[pos] = key[e];
+                    }
+                    ++pos;
                 }
-                ++pos;
             }
         }
     }
