@@ -297,10 +297,9 @@ __device__ __forceinline__ uint32_t key_of(T r2) {
 // split the n components; every lane returns the same value).  The
 // components come in groups of U per lane whose loads (clamped index,
 // masked afterwards) are all issued before any is used.
-template <int K, typename TX>
+template <int K, typename TX, int U = (K <= 8 ? 4 : 2)>
 __device__ __forceinline__ double exact_r_wave(const TX *__restrict__ X, int64_t ldx, int n,
                                                const double *P64t, int64_t i, int64_t j) {
-    constexpr int U = K <= 8 ? 4 : 2;
     const int lane = threadIdx.x & 63;
     const TX *xi = X + i * ldx, *xj = X + j * ldx;
     double v[K + 1];
@@ -620,7 +619,11 @@ __device__ __forceinline__ void rescore_cands(const SweepArgs<TX> &a, const Cand
         const uint32_t kv = cl.key[c];
         if (kv > T2b) continue;
         const int2 ij = cl.ij[c];
-        const double r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, a.P64t, ij.x, ij.y);
+        double r;
+        // one group of components when n <= 64 (no clamped extra loads; K <= 7,
+        // where the second instance fits the register budget)
+        if (K <= 7 && a.n <= kWave) r = exact_r_wave<K, TX, 1>(a.X, a.ldx, a.n, a.P64t, ij.x, ij.y);
+        else r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, a.P64t, ij.x, ij.y);
         ++wb.nwin;
         wb.nviol += bound_broken(r, (double)__uint_as_float(kv), a.e_abs, a.e_rel);
         if (lex_less(r, ij.x, ij.y, wb.r, wb.i, wb.j)) { wb.r = r; wb.i = ij.x; wb.j = ij.y; }
