@@ -21,11 +21,7 @@
 
 using namespace sap;
 
-// Grid sizing of the fused pass: half-tiles per pass block (the blocks
-// stride over the rest) and short pairs per short-pair block.
-#ifndef SAP_HALVES_PER_BLOCK
-#define SAP_HALVES_PER_BLOCK 8
-#endif
+// Grid sizing of the fused pass: short pairs per short-pair block.
 #ifndef SAP_SHORT_PER_BLOCK
 #define SAP_SHORT_PER_BLOCK 64
 #endif
@@ -79,6 +75,7 @@ struct sap_ctx {
     Partial *d_part = nullptr;   // pass-block results, then one per short-pair block
     DevResult *d_res = nullptr;
     int pass_grid = 0, short_grid = 0;
+    int sm_grid = 0;   // fused: blocks of the soft-min tile passes
     size_t tail_lds = 0;
 
     // soft-min (allocated on first use)
@@ -424,12 +421,21 @@ static sap_status init_fused(sap_ctx *h) {
     h->close_d = dtarget * std::pow(2.0, -msel / 4.0);
     h->e_abs = st.keep_max ? 2.0 * delta * std::sqrt((double)wmax * (1.0 + std::ldexp(1.0, -22))) : 0.0;
     h->e_rel = (h->k + 4) * kU32;
-    // SAP_HALVES_PER_BLOCK half-tiles per block of four wavefronts (the
-    // blocks stride over the rest when the grid is capped)
-    h->pass_grid = (int)std::min<int64_t>(ceil_div(2 * h->ntiles, SAP_HALVES_PER_BLOCK), 8192);
     // iteration: 64 short pairs per block (16 per wavefront, on the matrix
     // cores); the soft-min's short-pair blocks use the same grid size
     h->short_grid = h->nclose > 0 ? (int)std::min<int64_t>(ceil_div(h->nclose, SAP_SHORT_PER_BLOCK), 1024) : 0;
+    // pass blocks: with the short-pair blocks, one round of resident blocks
+    // (four per compute unit), and at least one half-tile per wavefront; the
+    // blocks stride over the rest of the tiles
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
+        cus = 256;
+    const int64_t slots = 4 * (int64_t)cus;
+    h->pass_grid = (int)std::max<int64_t>(
+        1, std::min<int64_t>(ceil_div(2 * h->ntiles, 4), std::max<int64_t>(slots / 4, slots - h->short_grid)));
+    // soft-min tile passes (three or four blocks per compute unit): eight
+    // half-tiles per block, many rounds
+    h->sm_grid = (int)std::min<int64_t>(ceil_div(2 * h->ntiles, 8), 8192);
     return SAP_OK;
 }
 
@@ -645,7 +651,7 @@ static sap_status sm_alloc(sap_ctx *h) {
     h->sm_chunks = (int)ceil_div(h->N, h->sm_rows);
     SAP_TRY(dalloc(h, &h->d_smP64t, sizeof(double) * h->n * K));
     SAP_TRY(dalloc(h, &h->d_smY, sizeof(float) * (size_t)h->Npad * h->kp));
-    SAP_TRY(dalloc(h, &h->d_smpart, sizeof(SmPart) * (size_t)(h->pass_grid + h->short_grid)));
+    SAP_TRY(dalloc(h, &h->d_smpart, sizeof(SmPart) * (size_t)(h->sm_grid + h->short_grid)));
     SAP_TRY(dalloc(h, &h->d_smZr, sizeof(float) * (size_t)nhalf * K * 32));
     SAP_TRY(dalloc(h, &h->d_smZc, sizeof(float) * (size_t)nhalf * K * 64));
     SAP_TRY(dalloc(h, &h->d_smZ, sizeof(double) * (size_t)h->N * K));
@@ -661,7 +667,7 @@ static SmArgs sm_args(sap_ctx *h, double tau) {
     a.invd2 = h->d_invd2;
     a.tiles = h->d_tiles;
     a.nhalf = 2 * h->ntiles;
-    a.npass = h->pass_grid;
+    a.npass = h->sm_grid;
     a.n = h->n;
     a.close = h->d_close;
     a.cd = h->d_cd;
@@ -692,10 +698,10 @@ static sap_status sm_forward(sap_ctx *h, const float *P, double tau, float *loss
     SAP_DISPATCH_K(K, SAP_TRY(launch(h, 5, "k_sm_prep", k_sm_prep<K, TX>,
                                      dim3((unsigned)(gemm_blocks + nshort)), blk, 0, a, X, h->ldx,
                                      h->N, (const double *)h->d_mu, h->d_smY, h->Npad, gemm_blocks, 0)));
-    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 3, "k_sm_fwd", k_sm_fwd<K>, dim3((unsigned)h->pass_grid), blk,
+    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 3, "k_sm_fwd", k_sm_fwd<K>, dim3((unsigned)h->sm_grid), blk,
                                      0, a)));
     SAP_TRY(launch(h, 5, "k_sm_fin", k_sm_fin, dim3(1), blk, 0, (const SmPart *)h->d_smpart,
-                   h->pass_grid + nshort, tau, loss, h->d_st));
+                   h->sm_grid + nshort, tau, loss, h->d_st));
     return SAP_OK;
 }
 
@@ -710,7 +716,7 @@ static sap_status sm_backward(sap_ctx *h, double tau, const float *grad_loss, fl
         SAP_DISPATCH_K(K, SAP_TRY(launch(h, 5, "k_sm_prep", k_sm_prep<K, TX>, dim3((unsigned)nshort),
                                          blk, 0, a, X, h->ldx, h->N, (const double *)h->d_mu,
                                          h->d_smY, h->Npad, 0, 1)));
-    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 4, "k_sm_bwd", k_sm_bwd<K>, dim3((unsigned)h->pass_grid), blk,
+    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 4, "k_sm_bwd", k_sm_bwd<K>, dim3((unsigned)h->sm_grid), blk,
                                      0, a)));
     SAP_DISPATCH_K(K, SAP_TRY(launch(h, 5, "k_sm_zred", k_sm_zred<K>, dim3((unsigned)h->nb), blk, 0, a,
                                      h->nb, h->N, (const int32_t *)h->d_rp_i,
