@@ -352,8 +352,11 @@ __device__ __forceinline__ uint32_t window_key(uint32_t gmin, double e_abs, doub
 // generously upward: T = (sqrt(m) (1 + e_rel) + 2 e_abs) / (1 - e_rel) = sqrt(m) wa + wb,
 // and T^2 (1 + 1e-6) exceeds the exact square by more than the few FP32
 // roundings of sqrt, multiply and add can lose.  A superset only costs
-// rescoring time, never correctness.
+// rescoring time, never correctness.  A smallest key that is no valid value
+// (an item of masked pairs only: negative or NaN bits) gets the empty window
+// 0, which none of that item's keys is at or below.
 __device__ __forceinline__ uint32_t item_window(uint32_t m, float wa, float wb) {
+    if (m >= 0x7f800000u) return 0u;
     const float t = __builtin_fmaf(__builtin_amdgcn_sqrtf(__uint_as_float(m)), wa, wb);
     return __float_as_uint(t * t * 1.000001f);
 }
