@@ -14,10 +14,13 @@
 
 #include "sap_common.h"
 
-// The kernels are compiled into this translation unit (one code object).
+// The K-independent kernels are compiled into this translation unit; the
+// kernels templated on K are compiled per K in sap_kinst.hip and reached
+// through the KLaunch launchers.
 #include "sap_init.hip"
 #include "sap_iter.hip"
 #include "sap_softmin.hip"
+#include "sap_launch.h"
 
 using namespace sap;
 
@@ -464,6 +467,23 @@ static sap_status launch(sap_ctx *h, int slot, const char *what, F kernel, dim3 
     return SAP_OK;
 }
 
+// Launch through a typed launcher fn(LaunchCfg) (the per-K kernels), with
+// the same profiling as launch().
+template <typename F>
+static sap_status launch_with(sap_ctx *h, int slot, const char *what, dim3 grid, dim3 block, uint32_t shmem,
+                              F &&fn) {
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (h->prof_on) {
+        SAP_TRY(ev_get(h, &ea));
+        SAP_TRY(ev_get(h, &eb));
+    }
+    const LaunchCfg c{grid, block, shmem, h->stream, ea, eb};
+    const hipError_t e = fn(c);
+    if (e != hipSuccess) return fail(h, SAP_ERR_DEVICE, "launch of %s: %s", what, hipGetErrorString(e));
+    if (ea) h->marks.push_back(sap_ctx::Mark{ea, eb, slot});
+    return SAP_OK;
+}
+
 template <typename TX>
 static SweepArgs<TX> sweep_args(sap_ctx *h, double *tr_min, int64_t *tr_ij, int32_t *tr_cert,
                                 int it) {
@@ -509,7 +529,9 @@ static sap_status launch_prep(sap_ctx *h) {
     const int K = h->k;
     const SweepArgs<TX> a = sweep_args<TX>(h, nullptr, nullptr, nullptr, 0);
     const dim3 g0((unsigned)(h->Npad / 64)), blk(kPairBlock);
-    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 0, "k_prep", k_prep<K, TX>, g0, blk, 0, a, h->d_mu, h->d_Y, h->Npad)));
+    SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 0, "k_prep", g0, blk, 0, [&](const LaunchCfg &c) {
+        return KLaunch<K, TX>::prep(c, a, h->d_mu, h->d_Y, h->Npad);
+    })));
     return SAP_OK;
 }
 
@@ -520,11 +542,9 @@ static sap_status launch_pass(sap_ctx *h) {
     const SweepArgs<TX> a = sweep_args<TX>(h, nullptr, nullptr, nullptr, 0);
     const int nshort = fused ? h->short_grid : 0;
     const dim3 g1((unsigned)(h->pass_grid + nshort)), blk(kPairBlock);
-    if (fused) {
-        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 1, "k_pass", k_pass<K, TX, true>, g1, blk, 0, a, nshort)));
-    } else {
-        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 1, "k_pass", k_pass<K, TX, false>, g1, blk, 0, a, 0)));
-    }
+    SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 1, "k_pass", g1, blk, 0, [&](const LaunchCfg &c) {
+        return KLaunch<K, TX>::pass(c, fused, a, nshort);
+    })));
     return SAP_OK;
 }
 
@@ -538,15 +558,10 @@ static sap_status launch_select(sap_ctx *h, int do_step, double *tr_min, int64_t
     const int pr_kind = fused ? 0 : (h->cfg.dtype == SAP_F64 ? 2 : 1);
     const uint32_t lds = (uint32_t)h->tail_lds;
     const dim3 blk(kPairBlock);
-    if (fused) {
-        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 2, "k_select", k_select<K, TX, true>, dim3(1), blk, lds,
-                                         a, nshort, h->d_P64t, h->d_Pr, pr_kind,
-                                         h->cfg.alpha, h->cfg.rule, do_step)));
-    } else {
-        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 2, "k_select", k_select<K, TX, false>, dim3(1), blk, lds,
-                                         a, nshort, h->d_P64t, h->d_Pr, pr_kind,
-                                         h->cfg.alpha, h->cfg.rule, do_step)));
-    }
+    SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 2, "k_select", dim3(1), blk, lds, [&](const LaunchCfg &c) {
+        return KLaunch<K, TX>::select(c, fused, a, nshort, h->d_P64t, h->d_Pr, pr_kind, h->cfg.alpha,
+                                      h->cfg.rule, do_step);
+    })));
     return SAP_OK;
 }
 
@@ -558,9 +573,11 @@ static sap_status launch_selprep(sap_ctx *h, double *tr_min, int64_t *tr_ij, int
     const int K = h->k;
     const SweepArgs<TX> a = sweep_args<TX>(h, tr_min, tr_ij, tr_cert, it);
     const dim3 g0((unsigned)(h->Npad / 64)), blk(kPairBlock);
-    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 6, "k_selprep", k_selprep<K, TX>, g0, blk, (uint32_t)h->tail_lds, a,
-                                     h->short_grid, h->d_P64t_alt, h->cfg.alpha, h->cfg.rule, h->d_mu,
-                                     h->d_Y, h->Npad)));
+    SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 6, "k_selprep", g0, blk, (uint32_t)h->tail_lds,
+                                          [&](const LaunchCfg &c) {
+        return KLaunch<K, TX>::selprep(c, a, h->short_grid, h->d_P64t_alt, h->cfg.alpha, h->cfg.rule,
+                                       h->d_mu, h->d_Y, h->Npad);
+    })));
     std::swap(h->d_P64t, h->d_P64t_alt);
     return SAP_OK;
 }
@@ -695,11 +712,12 @@ static sap_status sm_forward(sap_ctx *h, const float *P, double tau, float *loss
     const TX *X = static_cast<const TX *>(h->X);
     SAP_TRY(launch(h, 5, "k_sm_loadP", k_sm_loadP, dim3((unsigned)ceil_div((int64_t)h->n * K, 256)),
                    dim3(256), 0, P, h->n, K, h->d_smP64t));
-    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 5, "k_sm_prep", k_sm_prep<K, TX>,
-                                     dim3((unsigned)(gemm_blocks + nshort)), blk, 0, a, X, h->ldx,
-                                     h->N, (const double *)h->d_mu, h->d_smY, h->Npad, gemm_blocks, 0)));
-    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 3, "k_sm_fwd", k_sm_fwd<K>, dim3((unsigned)h->sm_grid), blk,
-                                     0, a)));
+    SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 5, "k_sm_prep", dim3((unsigned)(gemm_blocks + nshort)), blk, 0,
+                                          [&](const LaunchCfg &c) {
+        return KLaunch<K, TX>::sm_prep(c, a, X, h->ldx, h->N, h->d_mu, h->d_smY, h->Npad, gemm_blocks, 0);
+    })));
+    SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 3, "k_sm_fwd", dim3((unsigned)h->sm_grid), blk, 0,
+                                          [&](const LaunchCfg &c) { return KLaunch<K, TX>::sm_fwd(c, a); })));
     SAP_TRY(launch(h, 5, "k_sm_fin", k_sm_fin, dim3(1), blk, 0, (const SmPart *)h->d_smpart,
                    h->sm_grid + nshort, tau, loss, h->d_st));
     return SAP_OK;
@@ -713,15 +731,16 @@ static sap_status sm_backward(sap_ctx *h, double tau, const float *grad_loss, fl
     const dim3 blk(kPairBlock);
     const TX *X = static_cast<const TX *>(h->X);
     if (nshort > 0)
-        SAP_DISPATCH_K(K, SAP_TRY(launch(h, 5, "k_sm_prep", k_sm_prep<K, TX>, dim3((unsigned)nshort),
-                                         blk, 0, a, X, h->ldx, h->N, (const double *)h->d_mu,
-                                         h->d_smY, h->Npad, 0, 1)));
-    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 4, "k_sm_bwd", k_sm_bwd<K>, dim3((unsigned)h->sm_grid), blk,
-                                     0, a)));
-    SAP_DISPATCH_K(K, SAP_TRY(launch(h, 5, "k_sm_zred", k_sm_zred<K>, dim3((unsigned)h->nb), blk, 0, a,
-                                     h->nb, h->N, (const int32_t *)h->d_rp_i,
-                                     (const int32_t *)h->d_rp_j, (const int32_t *)h->d_permj,
-                                     h->d_smZ)));
+        SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 5, "k_sm_prep", dim3((unsigned)nshort), blk, 0,
+                                              [&](const LaunchCfg &c) {
+            return KLaunch<K, TX>::sm_prep(c, a, X, h->ldx, h->N, h->d_mu, h->d_smY, h->Npad, 0, 1);
+        })));
+    SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 4, "k_sm_bwd", dim3((unsigned)h->sm_grid), blk, 0,
+                                          [&](const LaunchCfg &c) { return KLaunch<K, TX>::sm_bwd(c, a); })));
+    SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 5, "k_sm_zred", dim3((unsigned)h->nb), blk, 0,
+                                          [&](const LaunchCfg &c) {
+        return KLaunch<K, TX>::sm_zred(c, a, h->nb, h->N, h->d_rp_i, h->d_rp_j, h->d_permj, h->d_smZ);
+    })));
     const unsigned slices = (unsigned)ceil_div((int64_t)h->n * K, 256);
     SAP_TRY(launch(h, 5, "k_sm_grad", k_sm_grad<TX>, dim3((unsigned)h->sm_chunks, slices), dim3(256), 0,
                    X, h->ldx, h->N, h->n, K, (const double *)h->d_mu, (const double *)h->d_smZ,
@@ -777,20 +796,8 @@ sap_status sap_init(const sap_config *cfg, const void *X, int64_t ldx, const dou
     h->tail_lds = sizeof(double) * ((size_t)h->k * h->n + 2 * (size_t)h->n);
     e = hipSuccess;
     SAP_DISPATCH_K(h->k, {
-        const void *fns[4] = {reinterpret_cast<const void *>(&k_select<K, float, true>),
-                              reinterpret_cast<const void *>(&k_select<K, float, false>),
-                              reinterpret_cast<const void *>(&k_select<K, double, true>),
-                              reinterpret_cast<const void *>(&k_select<K, double, false>)};
-        const void *fns_sp[2] = {reinterpret_cast<const void *>(&k_selprep<K, float>),
-                                 reinterpret_cast<const void *>(&k_selprep<K, double>)};
-        for (const void *f : fns)
-            if (e == hipSuccess)
-                e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)h->tail_lds);
-        for (const void *f : fns_sp)
-            if (e == hipSuccess)
-                e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)h->tail_lds);
+        e = KLaunch<K, float>::set_select_lds((int)h->tail_lds);
+        if (e == hipSuccess) e = KLaunch<K, double>::set_select_lds((int)h->tail_lds);
     });
     if (e != hipSuccess) return bail(fail(h, SAP_ERR_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(e)));
     e = hipStreamSynchronize(h->stream);

@@ -69,6 +69,19 @@ __device__ __forceinline__ int64_t pair_index(int64_t N, int64_t i, int64_t j) {
     return i * N - i * (i + 1) / 2 + (j - i - 1);
 }
 
+// Pair (i, j), i < j, of pair index q (inverse of pair_index).
+__device__ __forceinline__ void decode_pair(int64_t q, int64_t N, int64_t &i, int64_t &j) {
+    double b = 2.0 * (double)N - 1.0;
+    double disc = b * b - 8.0 * (double)q;
+    int64_t ii = (int64_t)floor((b - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
+    if (ii < 0) ii = 0;
+    if (ii > N - 2) ii = N - 2;
+    while (ii > 0 && pair_index(N, ii, ii + 1) > q) --ii;
+    while (ii < N - 2 && pair_index(N, ii + 1, ii + 2) <= q) ++ii;
+    i = ii;
+    j = q - pair_index(N, ii, ii + 1) + ii + 1;
+}
+
 __device__ __forceinline__ double load_x(const void *X, int dtype, int64_t off) {
     return dtype == SAP_F64 ? static_cast<const double *>(X)[off]
                             : static_cast<double>(static_cast<const float *>(X)[off]);
@@ -107,6 +120,15 @@ __device__ __forceinline__ void wave_min_lex(double &r, int32_t &i, int32_t &j) 
         if (lex_less(r2, i2, j2, r, i, j)) { r = r2; i = i2; j = j2; }
     }
 }
+
+// Launch geometry of one kernel on the handle's stream; ea / eb (may be
+// null) receive the dispatch's own start and end timestamps.
+struct LaunchCfg {
+    dim3 grid, block;
+    uint32_t shmem;
+    hipStream_t stream;
+    hipEvent_t ea, eb;
+};
 
 }  // namespace sap
 

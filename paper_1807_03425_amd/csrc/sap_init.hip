@@ -63,18 +63,6 @@ __global__ __launch_bounds__(256) void k_radius(const void *X, int dtype, int64_
 
 // ---------------------------------------------------------------- plain form
 
-__device__ __forceinline__ void decode_pair(int64_t q, int64_t N, int64_t &i, int64_t &j) {
-    double b = 2.0 * (double)N - 1.0;
-    double disc = b * b - 8.0 * (double)q;
-    int64_t ii = (int64_t)floor((b - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
-    if (ii < 0) ii = 0;
-    if (ii > N - 2) ii = N - 2;
-    while (ii > 0 && pair_index(N, ii, ii + 1) > q) --ii;
-    while (ii < N - 2 && pair_index(N, ii + 1, ii + 2) <= q) ++ii;
-    i = ii;
-    j = q - pair_index(N, ii, ii + 1) + ii + 1;
-}
-
 // S[l * pcols + q] = component l of the unit secant of pair q (computed in
 // FP64, stored in T).  Dropped pairs and the padding q >= p hold NaN.
 template <typename T>

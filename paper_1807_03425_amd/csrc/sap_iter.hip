@@ -1395,6 +1395,7 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
                    a.n >= 64 ? x0 : nullptr, m0);
 }
 
+#ifndef SAP_KINST   // K-independent kernels: compiled once, in the host runtime unit
 // ------------------------------------------------------------------ small helpers
 
 // The plain pass's n x k row-major copy of P in X's dtype, from the master.
@@ -1430,5 +1431,7 @@ __global__ void k_short_len(const TX *__restrict__ X, int64_t ldx, int n,
     }
     cd[e] = sqrt(d2);
 }
+
+#endif  // SAP_KINST
 
 }  // namespace sap

@@ -88,6 +88,7 @@ __device__ void block_lse(double m, double s, double tau, SmPart *out) {
     }
 }
 
+#ifndef SAP_KINST
 // P (n x k row-major FP32) -> k x n FP64.
 __global__ void k_sm_loadP(const float *__restrict__ P, int n, int k, double *__restrict__ P64t) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -95,6 +96,8 @@ __global__ void k_sm_loadP(const float *__restrict__ P, int n, int k, double *__
     const int l = e / k, q = e % k;
     P64t[(int64_t)q * n + l] = (double)P[e];
 }
+
+#endif
 
 // Short pairs in FP64 (c = P^T (x_i - x_j) on the matrix cores, 16 pairs per
 // wavefront, grid-stride).  Forward: the block's (min, sum) partial.
@@ -213,6 +216,7 @@ __global__ __launch_bounds__(kPairBlock) void k_sm_fwd(SmArgs a) {
     block_lse((double)m, s, a.tau, a.part + blockIdx.x);
 }
 
+#ifndef SAP_KINST
 // Final merge of the forward (one block): L = m - tau log s.
 __global__ __launch_bounds__(kPairBlock) void k_sm_fin(const SmPart *__restrict__ part, int nparts,
                                                        double tau, float *__restrict__ loss,
@@ -230,6 +234,8 @@ __global__ __launch_bounds__(kPairBlock) void k_sm_fin(const SmPart *__restrict_
         loss[0] = (float)L;
     }
 }
+
+#endif
 
 // Backward pass: one wavefront per half-tile (rows i = 64 bi + 32 half + 0..31,
 // columns j = 64 bj + lane).  Phase 1 (lane = column): a_ij and the column
@@ -412,6 +418,7 @@ __global__ __launch_bounds__(kPairBlock) void k_sm_zred(SmArgs a, int64_t nb, in
     }
 }
 
+#ifndef SAP_KINST
 // G_c = sum_{p in chunk c} (x_p - mu) z_p^T, one output element (l, q) per
 // thread (element e = q n + l: consecutive threads read consecutive x).
 template <typename TX>
@@ -461,5 +468,7 @@ __global__ __launch_bounds__(256) void k_sm_dP(const double *__restrict__ Gpart,
         dP[(int64_t)l * K + q] = (float)((double)grad_loss[0] * g);
     }
 }
+
+#endif
 
 }  // namespace sap
