@@ -21,8 +21,8 @@
  *  - Pairs are unordered, i < j, indexed q = i*N - i*(i+1)/2 + (j - i - 1).
  *    Argmin ties are broken by the smallest (i, j).
  *  - Work is enqueued on the stream given to sap_init (or sap_set_stream).
- *    Only sap_min_secant, sap_step with a non-NULL result, sap_info and
- *    sap_softmin_stats synchronise that stream.
+ *    Only sap_init, sap_min_secant, sap_step with a non-NULL result, sap_set_P,
+ *    sap_info, sap_softmin_bwd and sap_profile_read synchronise that stream.
  *  - A handle is not thread-safe; distinct handles are independent.
  *  - Errors are returned as status codes, never thrown.  SAP_ERR_DEVICE
  *    poisons the handle: afterwards only sap_last_error and sap_destroy work.
@@ -68,20 +68,33 @@ typedef enum {
 enum { SAP_F64 = 0, SAP_F32 = 1 };                       /* dtype of X           */
 enum { SAP_PLAIN = 0, SAP_FUSED = 1 };                   /* form of the pass     */
 enum { SAP_STEP_LITERAL = 0, SAP_STEP_NORMALIZED = 1 };  /* reading of the shift */
+/* Arithmetic of the fused form's Y = (X - mean) P (the projected points the
+ * coarse pass differences): FP64 on the matrix cores (default; the coarse
+ * error bound is then that of rounding Y to FP32), FP32 or BF16 inputs with
+ * FP32 accumulation (cheaper operands, a proportionally wider rescoring
+ * window; see sap_info's e_abs). */
+enum { SAP_GEMM_F64 = 0, SAP_GEMM_F32 = 1, SAP_GEMM_BF16 = 2 };
 
-/* Configuration (Algorithm 1's inputs: target dimension k, shift alpha; the
- * length threshold l of Sec. 7).
+/* Configuration: Algorithm 1's inputs (target dimension k, shift alpha), the
+ * length threshold l of Sec. 7 (min_len), and how the evaluation is carried
+ * out.
  *   N >= 2, 1 <= k <= min(n, 16), n*(k+3) <= 19200 (the FP64 update keeps its
  *   vectors in LDS), alpha in [0, 1], min_len >= 0.
  *   rule: SAP_STEP_LITERAL combines the unnormalised P P^T s and s - P P^T s
- *         (the paper's wording); SAP_STEP_NORMALIZED combines their unit
- *         vectors.
+ *         (the wording of Sec. 4 and Algorithm 1); SAP_STEP_NORMALIZED
+ *         combines their unit vectors.
  *   close_d: fused form only; pairs with d < close_d are evaluated in FP64
  *         every iteration.  < 0 selects it automatically: the cutoff at
  *         which the coarse error bound e_abs (see sap_info) is about 4e-6.
  *         close_cap bounds that list (0 = min(2^20, max(1024, p / n)));
  *         an automatic cutoff is lowered until the list fits, an explicit one
- *         that does not fit fails with SAP_ERR_CAPACITY. */
+ *         that does not fit fails with SAP_ERR_CAPACITY.
+ *   cand_cap: capacity of each wavefront's list of rescoring candidates,
+ *         1..128 (0 = 128).  A list that fills up keeps its smallest coarse
+ *         values; if that drops a pair of the proven window the result is
+ *         reported with certified = 0 (it is then the best of the pairs that
+ *         were rescored).
+ *   gemm: SAP_GEMM_F64 | SAP_GEMM_F32 | SAP_GEMM_BF16 (fused form). */
 typedef struct {
     int64_t N;
     int32_t n, k;
@@ -89,21 +102,28 @@ typedef struct {
     int32_t form;       /* SAP_PLAIN | SAP_FUSED                    */
     int32_t rule;       /* SAP_STEP_LITERAL | SAP_STEP_NORMALIZED   */
     int32_t close_cap;
+    int32_t cand_cap;
+    int32_t gemm;       /* SAP_GEMM_F64 | SAP_GEMM_F32 | SAP_GEMM_BF16 */
     double alpha;
     double min_len;
     double close_d;
 } sap_config;
 
-/* One evaluation of the secant set (Algorithm 1, the argmin step). */
+/* One evaluation of the secant set (Algorithm 1, the argmin step: the worst
+ * secant of the current P and its projected norm). */
 typedef struct {
     double min_norm;     /* FP64 min of ||P^T s|| over kept pairs              */
-    int64_t i, j;        /* its pair (i < j), smallest (i, j) on ties            */
+    double runner_up;    /* a lower bound of the second-smallest ||P^T s||
+                            (lexicographic order), exact if runner_up_exact   */
+    int64_t i, j;        /* the pair of min_norm (i < j), smallest (i, j) on ties */
     int64_t pair_index;  /* q(i, j)                                            */
     double coarse_min;   /* smallest coarse (FP32/FP64-pass) value; -1 if none */
     double window;       /* coarse values within this of coarse_min were rescored */
     int32_t certified;   /* 1: the pair is provably the FP64 argmin            */
+    int32_t runner_up_exact;
     int32_t n_rescored;  /* pairs evaluated in FP64 this iteration             */
     int32_t t;           /* basis vector replaced by the update (0-based)      */
+    int32_t n_units;     /* work items of the pass that held candidates        */
     int32_t reserved;
 } sap_min_result;
 
@@ -120,19 +140,32 @@ typedef struct {
     int64_t n_tiles;        /* tiles (fused) or chunks (plain) of the pair pass  */
 } sap_info_t;
 
-/* Create a handle: validate, allocate, check X is finite and P0 orthonormal,
- * and precompute the secant array (plain) or the tile-packed 1/d^2 array and
- * the short-pair list (fused).  P0 is n x k FP64.  stream is a hipStream_t
- * (NULL = the null stream).  On failure *out is NULL. */
+/* Create a handle for Algorithm 1's inputs (Sec. 4: the secant set of X --
+ * every unit secant (x_i - x_j)/||x_i - x_j||, i < j, minus those shorter than
+ * min_len, Sec. 7 -- the target dimension and the shift) and the starting
+ * projection P0 (n x k FP64, orthonormal columns).  Validates, allocates,
+ * checks that X is finite and P0 orthonormal, and precomputes the secant
+ * array (plain form: the matrix S with the secants as columns, Sec. 4) or the
+ * tile-packed 1/d^2 array and the short-pair list (fused form).  stream is a
+ * hipStream_t (NULL = the null stream).  Errors: SAP_ERR_INVALID_ARG,
+ * SAP_ERR_UNSUPPORTED, SAP_ERR_NONFINITE, SAP_ERR_NOT_ORTHONORMAL,
+ * SAP_ERR_NO_PAIRS, SAP_ERR_CAPACITY, SAP_ERR_OUT_OF_MEMORY, SAP_ERR_DEVICE.
+ * On failure *out is NULL. */
 sap_status sap_init(const sap_config *cfg, const void *X, int64_t ldx,
                     const double *P0, void *stream, sap_handle *out);
 
-/* Evaluate the current P: min, argmin and the rescoring record.  Synchronises. */
+/* Algorithm 1's argmin step for the current P (Sec. 4: the column of P^T S
+ * of smallest norm): min, argmin, runner-up and the rescoring record.
+ * Synchronises. */
 sap_status sap_min_secant(sap_handle h, sap_min_result *out);
 
-/* One iteration: evaluate, then apply the update to P.  With out == NULL it
- * is fully asynchronous; otherwise it synchronises and reports the
- * evaluation that drove the update. */
+/* One iteration of Algorithm 1 (Sec. 4): the argmin step, then the update of
+ * P from the worst secant s -- t = argmax_c |<p_c, s>| (smallest c on ties;
+ * if every product is zero, p_1 is replaced by s), modified Gram-Schmidt on
+ * (P P^T s, the other basis vectors in order), and the first vector set to the
+ * unit vector along (1 - alpha) P P^T s + alpha (s - P P^T s) -- in FP64.
+ * With out == NULL it is fully asynchronous; otherwise it synchronises and
+ * reports the evaluation that drove the update. */
 sap_status sap_step(sap_handle h, sap_min_result *out_or_null);
 
 /* Algorithm 1 from the current P: iters updates and iters+1 evaluations (the
@@ -145,15 +178,19 @@ sap_status sap_step(sap_handle h, sap_min_result *out_or_null);
 sap_status sap_run(sap_handle h, int32_t iters, double *min_trace,
                    int64_t *ij_trace, int32_t *cert_trace);
 
-/* Copy the FP64 master P out (n x k row-major device buffer) / replace it.
- * sap_set_P checks orthonormality (max |P^T P - I| <= 1e-6) and synchronises. */
+/* The current projection P of Algorithm 1 (Sec. 4: n x k, orthonormal
+ * columns p_1..p_k): copy the FP64 master out (n x k row-major device buffer;
+ * asynchronous) / replace it.  sap_set_P checks orthonormality
+ * (max |P^T P - I| <= 1e-6, else SAP_ERR_NOT_ORTHONORMAL; NaN/Inf:
+ * SAP_ERR_NONFINITE) and synchronises. */
 sap_status sap_get_P(sap_handle h, double *P_out);
 sap_status sap_set_P(sap_handle h, const double *P);
 
-/* Change the stream later work is enqueued on. */
+/* Change the stream later work is enqueued on (no device work). */
 sap_status sap_set_stream(sap_handle h, void *stream);
 
-/* Sizes and error-bound parameters.  Synchronises. */
+/* Sizes of the secant set (Sec. 4, Sec. 7) and the error-bound parameters of
+ * the coarse evaluation.  Synchronises. */
 sap_status sap_info(sap_handle h, sap_info_t *out);
 
 /* Soft-min surrogate of the minimum (not in the paper; a differentiable
@@ -171,14 +208,16 @@ sap_status sap_info(sap_handle h, sap_info_t *out);
 sap_status sap_softmin_fwd(sap_handle h, const float *P, double tau,
                            float *loss);
 
-/* Gradient at the P of the latest forward (P must be that same projection;
- * its contents are not read again):
+/* Gradient of the soft-min at the P of the latest forward:
  *   dP = g dL/dP = g sum_{kept i<j} w_ij s_ij (P^T s_ij)^T / r_ij,
  * w_ij = exp(-(r_ij - L)/tau) (sum w = 1), g = grad_loss[0] (device FP32).
  * Contracted as (X - mean)^T Z with z_i = sum_j a_ij (y_i - y_j),
  * a_ij = w_ij / (d_ij^2 r_ij): the weights are recomputed from Y and 1/d^2,
  * never stored.  Pairs with r_ij = 0 contribute nothing.  dP is n x k
- * row-major FP32, overwritten.  Deterministic.  Asynchronous. */
+ * row-major FP32, overwritten.  Deterministic.  P must hold, bit for bit,
+ * the projection passed to that forward, and tau must be the forward's:
+ * otherwise SAP_ERR_INVALID_ARG (P is compared with the forward's copy, so
+ * this call synchronises the stream before enqueuing the backward). */
 sap_status sap_softmin_bwd(sap_handle h, const float *P, double tau,
                            const float *grad_loss, float *dP);
 

@@ -27,6 +27,8 @@ STATUS = {0: "SAP_OK", 1: "SAP_ERR_INVALID_ARG", 2: "SAP_ERR_NONFINITE",
 SAP_F64, SAP_F32 = 0, 1
 SAP_PLAIN, SAP_FUSED = 0, 1
 SAP_STEP_LITERAL, SAP_STEP_NORMALIZED = 0, 1
+SAP_GEMM_F64, SAP_GEMM_F32, SAP_GEMM_BF16 = 0, 1, 2
+GEMMS = {"f64": SAP_GEMM_F64, "f32": SAP_GEMM_F32, "bf16": SAP_GEMM_BF16}
 
 
 class SapError(RuntimeError):
@@ -38,15 +40,17 @@ class SapError(RuntimeError):
 class sap_config(C.Structure):
     _fields_ = [("N", C.c_int64), ("n", C.c_int32), ("k", C.c_int32),
                 ("dtype", C.c_int32), ("form", C.c_int32), ("rule", C.c_int32),
-                ("close_cap", C.c_int32), ("alpha", C.c_double),
+                ("close_cap", C.c_int32), ("cand_cap", C.c_int32), ("gemm", C.c_int32),
+                ("alpha", C.c_double),
                 ("min_len", C.c_double), ("close_d", C.c_double)]
 
 
 class sap_min_result(C.Structure):
-    _fields_ = [("min_norm", C.c_double), ("i", C.c_int64), ("j", C.c_int64),
-                ("pair_index", C.c_int64), ("coarse_min", C.c_double),
-                ("window", C.c_double), ("certified", C.c_int32),
-                ("n_rescored", C.c_int32), ("t", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("min_norm", C.c_double), ("runner_up", C.c_double), ("i", C.c_int64),
+                ("j", C.c_int64), ("pair_index", C.c_int64), ("coarse_min", C.c_double),
+                ("window", C.c_double), ("certified", C.c_int32), ("runner_up_exact", C.c_int32),
+                ("n_rescored", C.c_int32), ("t", C.c_int32), ("n_units", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class sap_info_t(C.Structure):
@@ -122,7 +126,7 @@ class SapContext:
 
     def __init__(self, X, P0, form: str = "fused", alpha: float = 0.01,
                  min_len: float = 0.0, rule: str = "literal", close_d: float = -1.0,
-                 close_cap: int = 0, stream=None):
+                 close_cap: int = 0, cand_cap: int = 0, gemm: str = "f64", stream=None):
         import torch
         if X.dim() != 2 or X.device.type != "cuda" or X.stride(1) != 1:
             raise ValueError("X must be a 2-D cuda tensor with unit stride along n")
@@ -137,7 +141,8 @@ class SapContext:
                          dtype=SAP_F64 if X.dtype == torch.float64 else SAP_F32,
                          form={"plain": SAP_PLAIN, "fused": SAP_FUSED}[form],
                          rule={"literal": SAP_STEP_LITERAL, "normalized": SAP_STEP_NORMALIZED}[rule],
-                         close_cap=int(close_cap), alpha=float(alpha), min_len=float(min_len),
+                         close_cap=int(close_cap), cand_cap=int(cand_cap), gemm=GEMMS[gemm],
+                         alpha=float(alpha), min_len=float(min_len),
                          close_d=float(close_d))
         self._X = X                      # keep the borrowed buffer alive
         self._stream = stream
@@ -176,9 +181,10 @@ class SapContext:
     # -- evaluation / iteration
     @staticmethod
     def _res(r: sap_min_result) -> dict:
-        return dict(min_norm=r.min_norm, i=r.i, j=r.j, pair_index=r.pair_index,
-                    coarse_min=r.coarse_min, window=r.window, certified=r.certified,
-                    n_rescored=r.n_rescored, t=r.t, n_window_tiles=r.reserved)
+        return dict(min_norm=r.min_norm, runner_up=r.runner_up, runner_up_exact=r.runner_up_exact,
+                    i=r.i, j=r.j, pair_index=r.pair_index, coarse_min=r.coarse_min,
+                    window=r.window, certified=r.certified, n_rescored=r.n_rescored, t=r.t,
+                    n_window_tiles=r.n_units)
 
     def min_secant(self) -> dict:
         r = sap_min_result()
@@ -250,7 +256,8 @@ class SapContext:
         return loss
 
     def softmin_bwd(self, P, tau: float, grad_loss):
-        """grad_loss * dL/dP at the P of the last softmin_fwd (same tau)."""
+        """grad_loss * dL/dP at the P of the last softmin_fwd (same P, bit for
+        bit, and the same tau; otherwise SapError INVALID_ARG)."""
         import torch
         P = P.to(device=self._X.device, dtype=torch.float32).contiguous()
         g = grad_loss.to(device=self._X.device, dtype=torch.float32).reshape(1).contiguous()

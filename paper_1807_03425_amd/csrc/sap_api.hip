@@ -83,6 +83,7 @@ struct sap_ctx {
 
     // soft-min (allocated on first use)
     double *d_smP64t = nullptr;
+    float *d_smP32 = nullptr;         // the forward's P as passed (n x k FP32)
     float *d_smY = nullptr;
     SmPart *d_smpart = nullptr;
     float *d_smZr = nullptr, *d_smZc = nullptr;
@@ -197,6 +198,14 @@ static sap_status validate(const sap_config *c, int64_t ldx, const void *X, cons
     if (std::isnan(c->close_d) || std::isinf(c->close_d))
         return fail(nullptr, SAP_ERR_INVALID_ARG, "close_d must be finite (< 0 = automatic)");
     if (c->close_cap < 0) return fail(nullptr, SAP_ERR_INVALID_ARG, "close_cap must be >= 0");
+    if (c->cand_cap < 0 || c->cand_cap > kCandCap)
+        return fail(nullptr, SAP_ERR_INVALID_ARG, "cand_cap must lie in [0, %d] (0 = %d)", kCandCap, kCandCap);
+    if (c->gemm != SAP_GEMM_F64 && c->gemm != SAP_GEMM_F32 && c->gemm != SAP_GEMM_BF16)
+        return fail(nullptr, SAP_ERR_INVALID_ARG, "gemm must be SAP_GEMM_F64, SAP_GEMM_F32 or SAP_GEMM_BF16");
+    if (c->gemm != SAP_GEMM_F64)
+        return fail(nullptr, SAP_ERR_UNSUPPORTED, "only SAP_GEMM_F64 is built");
+    if (c->gemm != SAP_GEMM_F64 && c->form != SAP_FUSED)
+        return fail(nullptr, SAP_ERR_INVALID_ARG, "gemm selects the fused form's Y GEMM: plain form needs SAP_GEMM_F64");
     if (ldx < c->n) return fail(nullptr, SAP_ERR_INVALID_ARG, "ldx must be >= n");
     return SAP_OK;
 }
@@ -520,6 +529,7 @@ static SweepArgs<TX> sweep_args(sap_ctx *h, double *tr_min, int64_t *tr_ij, int3
     a.tr_ij = tr_ij;
     a.tr_cert = tr_cert;
     a.it = it;
+    a.cap = h->cfg.cand_cap > 0 ? h->cfg.cand_cap : kCandCap;
     return a;
 }
 
@@ -624,15 +634,18 @@ static sap_status read_result(sap_ctx *h, sap_min_result *out) {
     SAP_HIP(h, hipMemcpyAsync(&r, h->d_res, sizeof r, hipMemcpyDeviceToHost, h->stream));
     SAP_HIP(h, hipStreamSynchronize(h->stream));
     out->min_norm = r.min_norm;
+    out->runner_up = r.runner_up;
     out->i = r.i;
     out->j = r.j;
     out->pair_index = r.q;
     out->coarse_min = r.coarse_min;
     out->window = r.window;
     out->certified = r.certified;
+    out->runner_up_exact = r.runner_up_exact;
     out->n_rescored = r.n_rescored;
     out->t = r.t;
-    out->reserved = r.n_tiles;
+    out->n_units = r.n_tiles;
+    out->reserved = 0;
     return SAP_OK;
 }
 
@@ -667,6 +680,7 @@ static sap_status sm_alloc(sap_ctx *h) {
     h->sm_rows = std::max<int64_t>(64, ceil_div(h->N, 256));
     h->sm_chunks = (int)ceil_div(h->N, h->sm_rows);
     SAP_TRY(dalloc(h, &h->d_smP64t, sizeof(double) * h->n * K));
+    SAP_TRY(dalloc(h, &h->d_smP32, sizeof(float) * h->n * K));
     SAP_TRY(dalloc(h, &h->d_smY, sizeof(float) * (size_t)h->Npad * h->kp));
     SAP_TRY(dalloc(h, &h->d_smpart, sizeof(SmPart) * (size_t)(h->sm_grid + h->short_grid)));
     SAP_TRY(dalloc(h, &h->d_smZr, sizeof(float) * (size_t)nhalf * K * 32));
@@ -876,6 +890,7 @@ sap_status sap_softmin_fwd(sap_handle h, const float *P, double tau, float *loss
     if (!loss) return fail(h, SAP_ERR_INVALID_ARG, "null loss pointer");
     SAP_TRY(sm_alloc(h));
     h->sm_ready = false;
+    SAP_HIP(h, hipMemcpyAsync(h->d_smP32, P, sizeof(float) * h->n * h->k, hipMemcpyDeviceToDevice, h->stream));
     if (h->cfg.dtype == SAP_F64) SAP_TRY(sm_forward<double>(h, P, tau, loss));
     else SAP_TRY(sm_forward<float>(h, P, tau, loss));
     h->sm_ready = true;
@@ -890,6 +905,18 @@ sap_status sap_softmin_bwd(sap_handle h, const float *P, double tau, const float
     if (!grad_loss || !dP) return fail(h, SAP_ERR_INVALID_ARG, "null grad_loss or dP");
     if (!h->sm_ready || tau != h->sm_tau)
         return fail(h, SAP_ERR_INVALID_ARG, "sap_softmin_bwd must follow sap_softmin_fwd with the same tau");
+    {
+        // the gradient is that of the forward's P: P must be that projection
+        // (compared bit for bit with the forward's copy)
+        const size_t nk = (size_t)h->n * h->k;
+        std::vector<float> a(nk), b(nk);
+        SAP_HIP(h, hipMemcpyAsync(a.data(), P, sizeof(float) * nk, hipMemcpyDeviceToHost, h->stream));
+        SAP_HIP(h, hipMemcpyAsync(b.data(), h->d_smP32, sizeof(float) * nk, hipMemcpyDeviceToHost, h->stream));
+        SAP_HIP(h, hipStreamSynchronize(h->stream));
+        if (std::memcmp(a.data(), b.data(), sizeof(float) * nk) != 0)
+            return fail(h, SAP_ERR_INVALID_ARG,
+                        "sap_softmin_bwd: P differs from the P of the latest sap_softmin_fwd");
+    }
     if (h->cfg.dtype == SAP_F64) return sm_backward<double>(h, tau, grad_loss, dP);
     return sm_backward<float>(h, tau, grad_loss, dP);
 }

@@ -27,23 +27,31 @@ constexpr float kMaskClose = -2.0f;    // evaluated in FP64 from the close list
 // Per-block result of the pass: the best FP64-rescored pair of the block.
 struct Partial {
     double r;         // best FP64 r in the block (+inf if none)
-    int32_t i, j;     // its pair
+    double r2;        // second-smallest FP64 r evaluated in the block (+inf if none)
+    int32_t i, j;     // the pair of r
     int32_t n_rescored;
     int32_t n_units;  // work items (half-tiles / chunks) with rescored pairs
-    int32_t n_viol;   // rescored pairs whose coarse value broke the error bound
+    int32_t n_viol;   // rescored pairs whose coarse value broke the error bound,
+                      // plus candidates dropped for want of list space
     uint32_t kmin;    // smallest coarse key of the block (kKeyNone: none)
+    uint32_t limit;   // smallest candidate-key limit a full list imposed
+                      // (kKeyNone: none): keys above it were not rescored
+    int32_t pad;
 };
 
 // Device-resident record of the last evaluation (read back by the host).
 struct DevResult {
     double min_norm;
+    double runner_up;
     int64_t i, j, q;
     double coarse_min;
     double window;
     int32_t certified;
+    int32_t runner_up_exact;
     int32_t n_rescored;
     int32_t t;
     int32_t n_tiles;
+    int32_t pad;
 };
 
 // Mutable device-side scalars of a handle.

@@ -374,41 +374,58 @@ __device__ __forceinline__ int dpp_i32(int v) {
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
 }
 
-__device__ __forceinline__ void lex_pick(double &r, int32_t &i, int32_t &j, double r2, int32_t i2,
-                                         int32_t j2) {
-    if (lex_less(r2, i2, j2, r, i, j)) { r = r2; i = i2; j = j2; }
+// (r, i, j) <- the lexicographic minimum of (r, i, j) and (r', i', j'), and r2
+// <- the second-smallest value of the two top-2 sets: the smaller of the two
+// second values and the first value of the tuple that lost.  The same pair
+// on both sides (the lanes of a wavefront that rescored cooperatively hold
+// identical results) is one element: only the second values merge.
+__device__ __forceinline__ void lex_pick2(double &r, int32_t &i, int32_t &j, double &r2, double rb, int32_t ib,
+                                          int32_t jb, double r2b) {
+    if (ib == i && jb == j) {
+        r2 = fmin(r2, r2b);
+    } else if (lex_less(rb, ib, jb, r, i, j)) {
+        r2 = fmin(fmin(r2, r2b), r);
+        r = rb; i = ib; j = jb;
+    } else {
+        r2 = fmin(fmin(r2, r2b), rb);
+    }
 }
 
 template <int CTRL>
-__device__ __forceinline__ void lex_step_dpp(double &r, int32_t &i, int32_t &j) {
-    lex_pick(r, i, j, dpp_f64<CTRL>(r), dpp_i32<CTRL>(i), dpp_i32<CTRL>(j));
+__device__ __forceinline__ void lex_step2_dpp(double &r, int32_t &i, int32_t &j, double &r2) {
+    lex_pick2(r, i, j, r2, dpp_f64<CTRL>(r), dpp_i32<CTRL>(i), dpp_i32<CTRL>(j), dpp_f64<CTRL>(r2));
 }
 
-// Lexicographic (r, i, j) minimum over the wavefront, in every lane: the same
-// six exchange steps as wave_sum_fast (four DPP steps inside 16-lane rows,
-// then the permlane16 / permlane32 swaps, whose two results are the lane's
-// own tuple and its partner's, in either order: the minimum of the two does
-// not depend on that order).  No LDS traffic.
-__device__ __forceinline__ void wave_min_lex_fast(double &r, int32_t &i, int32_t &j) {
-    lex_step_dpp<0xB1>(r, i, j);
-    lex_step_dpp<0x4E>(r, i, j);
-    lex_step_dpp<0x141>(r, i, j);
-    lex_step_dpp<0x140>(r, i, j);
+// Lexicographic (r, i, j) minimum over the wavefront and the second-smallest
+// value r2 (over all lanes' top-2 sets), in every lane: the same six exchange
+// steps as wave_sum_fast (four DPP steps inside 16-lane rows, then the
+// permlane16 / permlane32 swaps, whose two results are the lane's own tuple
+// and its partner's, in either order: the merge of the two does not depend on
+// that order).  No LDS traffic.
+__device__ __forceinline__ void wave_min_lex2_fast(double &r, int32_t &i, int32_t &j, double &r2) {
+    lex_step2_dpp<0xB1>(r, i, j, r2);
+    lex_step2_dpp<0x4E>(r, i, j, r2);
+    lex_step2_dpp<0x141>(r, i, j, r2);
+    lex_step2_dpp<0x140>(r, i, j, r2);
     {
         const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(r), __double2loint(r), false, false);
         const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(r), __double2hiint(r), false, false);
+        const auto lo2 = __builtin_amdgcn_permlane16_swap(__double2loint(r2), __double2loint(r2), false, false);
+        const auto hi2 = __builtin_amdgcn_permlane16_swap(__double2hiint(r2), __double2hiint(r2), false, false);
         const auto ii = __builtin_amdgcn_permlane16_swap(i, i, false, false);
         const auto jj = __builtin_amdgcn_permlane16_swap(j, j, false, false);
-        r = __hiloint2double(hi[0], lo[0]); i = ii[0]; j = jj[0];
-        lex_pick(r, i, j, __hiloint2double(hi[1], lo[1]), ii[1], jj[1]);
+        r = __hiloint2double(hi[0], lo[0]); i = ii[0]; j = jj[0]; r2 = __hiloint2double(hi2[0], lo2[0]);
+        lex_pick2(r, i, j, r2, __hiloint2double(hi[1], lo[1]), ii[1], jj[1], __hiloint2double(hi2[1], lo2[1]));
     }
     {
         const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(r), __double2loint(r), false, false);
         const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(r), __double2hiint(r), false, false);
+        const auto lo2 = __builtin_amdgcn_permlane32_swap(__double2loint(r2), __double2loint(r2), false, false);
+        const auto hi2 = __builtin_amdgcn_permlane32_swap(__double2hiint(r2), __double2hiint(r2), false, false);
         const auto ii = __builtin_amdgcn_permlane32_swap(i, i, false, false);
         const auto jj = __builtin_amdgcn_permlane32_swap(j, j, false, false);
-        r = __hiloint2double(hi[0], lo[0]); i = ii[0]; j = jj[0];
-        lex_pick(r, i, j, __hiloint2double(hi[1], lo[1]), ii[1], jj[1]);
+        r = __hiloint2double(hi[0], lo[0]); i = ii[0]; j = jj[0]; r2 = __hiloint2double(hi2[0], lo2[0]);
+        lex_pick2(r, i, j, r2, __hiloint2double(hi[1], lo[1]), ii[1], jj[1], __hiloint2double(hi2[1], lo2[1]));
     }
 }
 
@@ -437,29 +454,30 @@ __device__ __forceinline__ uint32_t wave_min_u32_fast(uint32_t v) {
     return min((uint32_t)b[0], (uint32_t)b[1]);
 }
 
-// Block-wide reduction of a per-thread (r, i, j), counters and coarse minimum
-// into *out (written by thread 0).  All 256 threads must call it.
-__device__ void block_reduce_partial(double r, int32_t i, int32_t j, int32_t nres, int32_t ntl,
-                                     int32_t nviol, uint32_t kmin, Partial *out) {
+// Block-wide reduction of a per-thread top-2 (r, i, j; r2), counters, the
+// coarse minimum and the candidate-key limit into *out (written by thread 0).
+// All 256 threads must call it.
+__device__ void block_reduce_partial(double r, int32_t i, int32_t j, double r2, int32_t nres, int32_t ntl,
+                                     int32_t nviol, uint32_t kmin, uint32_t limit, Partial *out) {
     __shared__ Partial sb[kPairBlock / kWave];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    wave_min_lex_fast(r, i, j);
+    wave_min_lex2_fast(r, i, j, r2);
     nres = wave_sum_i32_fast(nres);
     ntl = wave_sum_i32_fast(ntl);
     nviol = wave_sum_i32_fast(nviol);
     kmin = wave_min_u32_fast(kmin);
-    if (lane == 0) sb[wv] = Partial{r, i, j, nres, ntl, nviol, kmin};
+    limit = wave_min_u32_fast(limit);
+    if (lane == 0) sb[wv] = Partial{r, r2, i, j, nres, ntl, nviol, kmin, limit, 0};
     __syncthreads();
     if (threadIdx.x == 0) {
         Partial b = sb[0];
         for (int w = 1; w < kPairBlock / kWave; ++w) {
-            if (lex_less(sb[w].r, sb[w].i, sb[w].j, b.r, b.i, b.j)) {
-                b.r = sb[w].r; b.i = sb[w].i; b.j = sb[w].j;
-            }
+            lex_pick2(b.r, b.i, b.j, b.r2, sb[w].r, sb[w].i, sb[w].j, sb[w].r2);
             b.n_rescored += sb[w].n_rescored;
             b.n_units += sb[w].n_units;
             b.n_viol += sb[w].n_viol;
             b.kmin = min(b.kmin, sb[w].kmin);
+            b.limit = min(b.limit, sb[w].limit);
         }
         *out = b;
     }
@@ -503,6 +521,7 @@ struct SweepArgs {
     int64_t *tr_ij;
     int32_t *tr_cert;
     int it;
+    int cap;              // candidate-list capacity per wavefront, 1..kCandCap
 };
 
 // Candidates of a pass block.  The block keeps its running minimum key in
@@ -514,69 +533,130 @@ struct SweepArgs {
 // candidates (i, j, key) to its LDS list during the pass; after the pass the
 // block keeps those with key <= T2(block minimum) and rescores them in FP64
 // (wavefront-cooperatively), re-checking each coarse value against the
-// bound.  A full list is first pruned to the current window; if it is still
-// full, the candidate is dropped and the block's result marked uncertified
-// (never silently).
-constexpr int kCandCap = 128;   // candidates per wavefront
+// bound.
+//
+// A list that would overflow is first pruned to the current window.  If it
+// would still overflow, the wavefront keeps its smallest keys: it lowers a
+// key limit (only ever lowered) to the largest value that leaves at most
+// three quarters of the capacity in the list, drops every entry above it and
+// admits only keys at or below it from then on.  The limit is reported with
+// the block's result; the evaluation stays certified as long as every limit
+// is at or above the window of the global coarse minimum (no window pair was
+// dropped), and is reported uncertified otherwise -- never silently wrong.
+constexpr int kCandCap = 128;   // candidates per wavefront (largest capacity)
 
 struct CandList {
     int2 *ij;
     uint32_t *key;
-    int *cnt;       // one LDS word: hands the pruned count to every lane
     int n;          // wavefront-uniform
-    int lost;       // candidates dropped for lack of space
+    int cap;        // capacity, 1..kCandCap
+    int lost;       // candidates dropped although no limit excluded them
+    uint32_t limit; // candidate-key limit (kKeyNone: none)
 };
 
 struct WaveBest {
-    double r;
+    double r, r2;   // best FP64 r (its pair i, j) and the second-smallest value
     int32_t i, j, nwin, nviol, nunits;
 };
 
-// Append the lanes' keys that are <= T2 (the window of the block's running
-// minimum) to the wavefront's list.  key[e] belongs to the lane's pair
-// pair(e, i, j); lmin is the lane's smallest key.  The few lanes holding
-// candidates write their own entries, at offsets from a running count over
-// those lanes, so no key has to move between lanes.  A full list is first
-// pruned to T2; entries that still do not fit are counted as lost.
+// Keep the list entries with key <= th, in order (lane-parallel: lane L holds
+// entries L and L + 64; every entry is read before any is written).
+__device__ __forceinline__ void prune_cands(CandList &cl, uint32_t th) {
+    const int lane = threadIdx.x & 63;
+    const bool v0 = lane < cl.n, v1 = lane + kWave < cl.n;
+    int2 ij0 = make_int2(0, 0), ij1 = make_int2(0, 0);
+    uint32_t k0 = kKeyNone, k1 = kKeyNone;
+    if (v0) { ij0 = cl.ij[lane]; k0 = cl.key[lane]; }
+    if (v1) { ij1 = cl.ij[lane + kWave]; k1 = cl.key[lane + kWave]; }
+    const bool keep0 = v0 && k0 <= th, keep1 = v1 && k1 <= th;
+    const uint64_t m0 = __ballot(keep0), m1 = __ballot(keep1);
+    const int below0 = __builtin_amdgcn_mbcnt_hi((uint32_t)(m0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m0, 0));
+    const int below1 = __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0));
+    const int n0 = __builtin_popcountll(m0);
+    __builtin_amdgcn_wave_barrier();
+    if (keep0) { cl.ij[below0] = ij0; cl.key[below0] = k0; }
+    if (keep1) { cl.ij[n0 + below1] = ij1; cl.key[n0 + below1] = k1; }
+    __builtin_amdgcn_wave_barrier();
+    cl.n = n0 + __builtin_popcountll(m1);
+}
+
+// The largest key bound th <= te such that at most `target` keys -- list
+// entries plus the lane keys flagged in `bits` -- are <= th, built bit by bit
+// from the top (the count is monotone in th); but never below the smallest of
+// those keys (when that key alone occurs more than `target` times, the list
+// fills with it and the rest is counted as lost).
+template <int NK>
+__device__ __forceinline__ uint32_t cand_limit(const CandList &cl, const uint32_t (&key)[NK], uint32_t bits,
+                                               uint32_t te, int target) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t k0 = lane < cl.n ? cl.key[lane] : kKeyNone;
+    const uint32_t k1 = lane + kWave < cl.n ? cl.key[lane + kWave] : kKeyNone;
+    uint32_t th = 0;
+#pragma unroll 1
+    for (int b = 31; b >= 0; --b) {
+        const uint32_t t = th | (1u << b);
+        if (t > te) continue;   // wavefront-uniform
+        int c = (k0 <= t ? 1 : 0) + (k1 <= t ? 1 : 0);
+#pragma unroll
+        for (int e = 0; e < NK; ++e) c += (((bits >> e) & 1u) && key[e] <= t) ? 1 : 0;
+        if (wave_sum_i32_fast(c) <= target) th = t;
+    }
+    uint32_t m = min(k0, k1);
+#pragma unroll
+    for (int e = 0; e < NK; ++e) m = ((bits >> e) & 1u) ? min(m, key[e]) : m;
+    return max(th, wave_min_u32_fast(m));
+}
+
+// Append the lanes' keys that are <= min(T2, limit) (T2: the window of the
+// block's running minimum) to the wavefront's list.  key[e] belongs to the
+// lane's pair pair(e, i, j); lmin is the lane's smallest key.  The few lanes
+// holding candidates write their own entries, at offsets from a running count
+// over those lanes, so no key has to move between lanes.
 template <int NK, typename PairOf>
 __device__ __forceinline__ void emit_cands(CandList &cl, const uint32_t (&key)[NK], uint32_t lmin,
                                            uint32_t T2, PairOf pair, WaveBest &wb) {
     const int lane = threadIdx.x & 63;
+    uint32_t te = min(T2, cl.limit);
     uint32_t bits = 0;
-    if (lmin <= T2) {
+    if (lmin <= te) {
 #pragma unroll
-        for (int e = 0; e < NK; ++e) bits |= (key[e] <= T2 ? 1u : 0u) << e;
+        for (int e = 0; e < NK; ++e) bits |= (key[e] <= te ? 1u : 0u) << e;
     }
-    const int cnt = __builtin_popcount(bits);
-    uint64_t lanes = __ballot(cnt > 0);
-    if (!lanes) return;
+    int cnt = __builtin_popcount(bits);
+    if (!__ballot(cnt > 0)) return;
     ++wb.nunits;
-    int base = 0, tot = 0;
+    int tot = wave_sum_i32_fast(cnt);
+    if (cl.n + tot > cl.cap) {
+        // rare: prune to the current window, then, if still full, keep the
+        // smallest keys under a lowered limit
+        prune_cands(cl, te);
+        if (cl.n + tot > cl.cap) {
+            const uint32_t th = cand_limit<NK>(cl, key, bits, te, max(1, (3 * cl.cap) / 4));
+            cl.limit = th;
+            te = th;
+            prune_cands(cl, th);
+#pragma unroll
+            for (int e = 0; e < NK; ++e)
+                if (key[e] > th) bits &= ~(1u << e);
+            cnt = __builtin_popcount(bits);
+            tot = wave_sum_i32_fast(cnt);
+        }
+    }
+    uint64_t lanes = __ballot(cnt > 0);
+    int base = 0, run = 0;
 #pragma unroll 1
     while (lanes) {
         const int ln = __builtin_ctzll(lanes);
         lanes &= lanes - 1;
-        if (lane == ln) base = tot;
-        tot += __builtin_amdgcn_readlane(cnt, ln);
-    }
-    if (cl.n + tot > kCandCap) {
-        // prune to the current window (one lane, in order; rare)
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) {
-            int w = 0;
-            for (int c = 0; c < cl.n; ++c)
-                if (cl.key[c] <= T2) { cl.ij[w] = cl.ij[c]; cl.key[w] = cl.key[c]; ++w; }
-            *cl.cnt = w;
-        }
-        __builtin_amdgcn_wave_barrier();
-        cl.n = __builtin_amdgcn_readfirstlane(*cl.cnt);
+        if (lane == ln) base = run;
+        run += __builtin_amdgcn_readlane(cnt, ln);
     }
     if (bits) {
         int pos = cl.n + base;
         if ((bits & (bits - 1u)) == 0u) {
             // one key in the window: it is the lane's smallest (the usual
             // case, a new running minimum)
-            if (pos < kCandCap) {
+            if (pos < cl.cap) {
                 int32_t i, j;
                 pair(__builtin_ctz(bits), i, j);
                 cl.ij[pos] = make_int2(i, j);
@@ -586,7 +666,7 @@ __device__ __forceinline__ void emit_cands(CandList &cl, const uint32_t (&key)[N
 #pragma unroll
             for (int e = 0; e < NK; ++e) {
                 if ((bits >> e) & 1u) {
-                    if (pos < kCandCap) {
+                    if (pos < cl.cap) {
                         int32_t i, j;
                         pair(e, i, j);
                         cl.ij[pos] = make_int2(i, j);
@@ -598,8 +678,8 @@ __device__ __forceinline__ void emit_cands(CandList &cl, const uint32_t (&key)[N
         }
     }
     __builtin_amdgcn_wave_barrier();
-    const int room = kCandCap - cl.n;
-    if (tot > room) cl.lost += tot - room;
+    const int room = cl.cap - cl.n;
+    if (tot > room) cl.lost += tot - room;   // only if th = 0 still admitted too many
     cl.n += tot < room ? tot : room;
 }
 
@@ -629,7 +709,12 @@ __device__ __forceinline__ void rescore_cands(const SweepArgs<TX> &a, const Cand
         else r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, a.P64t, ij.x, ij.y);
         ++wb.nwin;
         wb.nviol += bound_broken(r, (double)__uint_as_float(kv), a.e_abs, a.e_rel);
-        if (lex_less(r, ij.x, ij.y, wb.r, wb.i, wb.j)) { wb.r = r; wb.i = ij.x; wb.j = ij.y; }
+        if (lex_less(r, ij.x, ij.y, wb.r, wb.i, wb.j)) {
+            wb.r2 = wb.r;
+            wb.r = r; wb.i = ij.x; wb.j = ij.y;
+        } else {
+            wb.r2 = fmin(wb.r2, r);
+        }
     }
 }
 
@@ -648,8 +733,8 @@ __device__ __forceinline__ void finish_pass_block(const SweepArgs<TX> &a, const 
     if (run < 0x7f800000u) rescore_cands<K, TX>(a, cl, item_window(run, a.wa, a.wb), wb);
     wb.nviol += cl.lost;   // dropped candidates: the result is not certified
     const int lane = threadIdx.x & 63;
-    block_reduce_partial(wb.r, wb.i, wb.j, lane == 0 ? wb.nwin : 0, lane == 0 ? wb.nunits : 0,
-                         lane == 0 ? wb.nviol : 0, kmin, out);
+    block_reduce_partial(wb.r, wb.i, wb.j, wb.r2, lane == 0 ? wb.nwin : 0, lane == 0 ? wb.nunits : 0,
+                         lane == 0 ? wb.nviol : 0, kmin, cl.limit, out);
 }
 
 // Fused pass block pb.  Wavefront w = 4 pb + slot takes work items
@@ -669,7 +754,6 @@ __device__ void fused_pass_block(const SweepArgs<TX> &a, int pb) {
     __shared__ float4 s_y[kPairBlock / kWave][32 * kMaxK / 4];
     __shared__ int2 s_cij[kPairBlock / kWave][kCandCap];
     __shared__ uint32_t s_ckey[kPairBlock / kWave][kCandCap];
-    __shared__ int s_ccnt[kPairBlock / kWave];
     __shared__ uint32_t s_run;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -685,8 +769,8 @@ __device__ void fused_pass_block(const SweepArgs<TX> &a, int pb) {
     constexpr int IPT = 16 / G;              // items per tile
     const int64_t nitem = a.nhalf * (8 / G);
     const int nf4 = G * kp;                  // float4 count of the item's 4G rows of Y (<= 128)
-    WaveBest wb{__builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0};
-    CandList cl{s_cij[wv], s_ckey[wv], &s_ccnt[wv], 0, 0};
+    WaveBest wb{__builtin_huge_val(), __builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0};
+    CandList cl{s_cij[wv], s_ckey[wv], 0, a.cap, 0, kKeyNone};
     uint32_t kmin = kKeyNone;   // the wavefront's smallest key
     int64_t h = (int64_t)pb * (kPairBlock / kWave) + wv;
     // loads of item h: weights, tile, y_j, two float4 of the y_i rows per lane
@@ -757,14 +841,13 @@ template <int K, typename TX>
 __device__ void plain_pass_block(const SweepArgs<TX> &a, int pb) {
     __shared__ int2 s_cij[kPairBlock / kWave][kCandCap];
     __shared__ uint32_t s_ckey[kPairBlock / kWave][kCandCap];
-    __shared__ int s_ccnt[kPairBlock / kWave];
     __shared__ uint32_t s_run;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t wid = (int64_t)pb * (kPairBlock / kWave) + wv;
     const int64_t nw = (int64_t)a.npass * (kPairBlock / kWave);
-    WaveBest wb{__builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0};
-    CandList cl{s_cij[wv], s_ckey[wv], &s_ccnt[wv], 0, 0};
+    WaveBest wb{__builtin_huge_val(), __builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0};
+    CandList cl{s_cij[wv], s_ckey[wv], 0, a.cap, 0, kKeyNone};
     uint32_t kmin = kKeyNone;   // the wavefront's smallest key
     if (threadIdx.x == 0) s_run = kKeyNone;
     __syncthreads();
@@ -843,7 +926,7 @@ __device__ void short_block(const SweepArgs<TX> &a, int sb, int nshort) {
     const int lane = threadIdx.x & 63;
     const int m = lane & 15, kk = lane >> 4;
     const int64_t ngroups = (a.nclose + 15) / 16;
-    double best = __builtin_huge_val();
+    double best = __builtin_huge_val(), second = __builtin_huge_val();
     int32_t bi = 0x7fffffff, bj = 0x7fffffff, cnt = 0;
     for (int64_t g16 = (int64_t)sb * (kPairBlock / kWave) + (threadIdx.x >> 6); g16 < ngroups;
          g16 += (int64_t)nshort * (kPairBlock / kWave)) {
@@ -863,11 +946,11 @@ __device__ void short_block(const SweepArgs<TX> &a, int sb, int nshort) {
             if (m == 0 && e < a.nclose) {
                 const double r = sqrt(q2) / dv;
                 ++cnt;
-                if (lex_less(r, pi, pj, best, bi, bj)) { best = r; bi = pi; bj = pj; }
+                lex_pick2(best, bi, bj, second, r, pi, pj, __builtin_huge_val());
             }
         }
     }
-    block_reduce_partial(best, bi, bj, cnt, 0, 0, kKeyNone, a.part + a.npass + sb);
+    block_reduce_partial(best, bi, bj, second, cnt, 0, 0, kKeyNone, kKeyNone, a.part + a.npass + sb);
 }
 
 // Selection (one block, after the pass): the lexicographic minimum of every
@@ -876,11 +959,20 @@ __device__ void short_block(const SweepArgs<TX> &a, int sb, int nshort) {
 // loaded per step, all before any is used (each step is a round trip to
 // memory written by other dies' caches).  Returns the winning pair in
 // every thread (i < 0 if there is none).
+//
+// Certified: no rescored pair broke the coarse bound, no candidate was lost,
+// and every block's candidate-key limit lies at or above the window of the
+// global coarse minimum.  The runner-up: every pair left unevaluated in FP64
+// has a coarse value above that window (or above its block's limit), hence a
+// true value above r_lo = (sqrt(min(window, limit)) - e_abs) / (1 + e_rel);
+// the reported runner_up is min(second-smallest evaluated value, r_lo), a
+// lower bound of the true runner-up, exact when the evaluated value is the
+// smaller.
 template <int K, typename TX, bool FUSED>
 __device__ int2 select_min(const SweepArgs<TX> &a, int nparts, bool record) {
-    double best = __builtin_huge_val();
+    double best = __builtin_huge_val(), second = __builtin_huge_val();
     int32_t bi = 0x7fffffff, bj = 0x7fffffff, nres = 0, nunits = 0, nviol = 0;
-    uint32_t kmin = kKeyNone;
+    uint32_t kmin = kKeyNone, limit = kKeyNone;
 #pragma unroll 1
     for (int base = 0; base < nparts; base += 8 * kPairBlock) {
         Partial p[8];
@@ -890,27 +982,41 @@ __device__ int2 select_min(const SweepArgs<TX> &a, int nparts, bool record) {
             // neutral element past the end: a guarded load would wait alone
             const int ix = base + u * kPairBlock + (int)threadIdx.x;
             p[u] = a.part[min(ix, nparts - 1)];
-            if (ix >= nparts) p[u] = Partial{__builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0, kKeyNone};
+            if (ix >= nparts)
+                p[u] = Partial{__builtin_huge_val(), __builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0,
+                               kKeyNone, kKeyNone, 0};
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            if (lex_less(p[u].r, p[u].i, p[u].j, best, bi, bj)) { best = p[u].r; bi = p[u].i; bj = p[u].j; }
+            lex_pick2(best, bi, bj, second, p[u].r, p[u].i, p[u].j, p[u].r2);
             nres += p[u].n_rescored;
             nunits += p[u].n_units;
             nviol += p[u].n_viol;
             kmin = min(kmin, p[u].kmin);
+            limit = min(limit, p[u].limit);
         }
     }
     __shared__ Partial s_fin;
-    block_reduce_partial(best, bi, bj, nres, nunits, nviol, kmin, &s_fin);
+    block_reduce_partial(best, bi, bj, second, nres, nunits, nviol, kmin, limit, &s_fin);
     if (record && threadIdx.x == 0) {
         const Partial f = s_fin;
         double coarse, tr;
         (void)window_key(f.kmin, a.e_abs, a.e_rel, &coarse, &tr);
         const bool found = f.r < __builtin_huge_val();
-        const int cert = (found && f.n_viol == 0) ? 1 : 0;
+        const uint32_t wkey = f.kmin < 0x7f800000u ? item_window(f.kmin, a.wa, a.wb) : 0u;
+        const int cert = (found && f.n_viol == 0 && f.limit >= wkey) ? 1 : 0;
+        // lower bound of every unevaluated pair's true value
+        double r_lo = __builtin_huge_val();
+        if (coarse >= 0.0) {
+            double t = tr;
+            if (f.limit != kKeyNone) t = fmin(t, sqrt((double)__uint_as_float(f.limit)));
+            r_lo = (t - a.e_abs) / (1.0 + a.e_rel) * (1.0 - 1e-9);
+        }
+        const double ru = fmin(f.r2, r_lo);
         DevResult *res = a.res;
         res->min_norm = f.r;
+        res->runner_up = ru;
+        res->runner_up_exact = (cert && f.r2 <= r_lo) ? 1 : 0;
         res->i = found ? f.i : -1;
         res->j = found ? f.j : -1;
         res->q = found ? pair_index(a.N, f.i, f.j) : -1;

@@ -243,10 +243,12 @@ __global__ __launch_bounds__(kPairBlock) void k_sm_fin(const SmPart *__restrict_
 // stride 65: conflict-free both ways).  Phase 2 (lane = row i = lane % 32,
 // column half lane / 32): z_i += a_ij (y_i - y_j) over its 32 columns, then the
 // two halves are added.  Partials go to Zr / Zc, component-major per half-tile.
-// LDS sized for K's padded row length, and at most 168 registers: three
-// blocks (three wavefronts per SIMD) fit a compute unit.
+// LDS sized for K's padded row length: 37.9 KB (K <= 4) to 57.9 KB (K >= 13)
+// per block.  Three blocks (three wavefronts per SIMD, at most 168 registers)
+// fit a compute unit's 160 KB for K <= 12; two for K >= 13, which then keep
+// up to 256 registers.
 template <int K>
-__global__ __launch_bounds__(kPairBlock, 3) void k_sm_bwd(SmArgs a) {
+__global__ __launch_bounds__(kPairBlock, K <= 12 ? 3 : 2) void k_sm_bwd(SmArgs a) {
     constexpr int KP = K <= 4 ? 4 : (K <= 8 ? 8 : (K <= 12 ? 12 : 16));   // the Y row length kp
     __shared__ float4 s_y[kPairBlock / kWave][32 * KP / 4];
     __shared__ float4 s_yc[kPairBlock / kWave][64 * KP / 4];

@@ -29,35 +29,38 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(sap._SIGS)
 
 
+MIRRORED = ("sap_config", "sap_min_result", "sap_info_t", "sap_profile_t")
+
+
 def test_struct_layout_matches_header(tmp_path):
+    """Every field of every struct the binding mirrors sits at the header's
+    offset, and the sizes agree."""
+    lines = []
+    for name in MIRRORED:
+        cls = getattr(sap, name)
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'F({name}, {f})')
     prog = tmp_path / "layout.c"
+    body = "\n  ".join(lines)
     prog.write_text(f"""
 #include <stdio.h>
 #include <stddef.h>
 #include "{HEADER}"
 #define F(T, m) printf("%s.%s %zu\\n", #T, #m, offsetof(T, m));
 int main(void) {{
-  printf("sap_config %zu\\n", sizeof(sap_config));
-  printf("sap_min_result %zu\\n", sizeof(sap_min_result));
-  printf("sap_info_t %zu\\n", sizeof(sap_info_t));
-  F(sap_config, alpha) F(sap_config, close_d) F(sap_config, close_cap)
-  F(sap_min_result, certified) F(sap_min_result, reserved) F(sap_info_t, n_tiles)
+  {body}
   return 0;
 }}""")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(prog)], check=True)
     out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True,
                                                         text=True, check=True).stdout.split("\n") if l)
-    assert int(out["sap_config"]) == C.sizeof(sap.sap_config)
-    assert int(out["sap_min_result"]) == C.sizeof(sap.sap_min_result)
-    assert int(out["sap_info_t"]) == C.sizeof(sap.sap_info_t)
-    for key, (cls, field) in {"sap_config.alpha": (sap.sap_config, "alpha"),
-                              "sap_config.close_d": (sap.sap_config, "close_d"),
-                              "sap_config.close_cap": (sap.sap_config, "close_cap"),
-                              "sap_min_result.certified": (sap.sap_min_result, "certified"),
-                              "sap_min_result.reserved": (sap.sap_min_result, "reserved"),
-                              "sap_info_t.n_tiles": (sap.sap_info_t, "n_tiles")}.items():
-        assert int(out[key]) == getattr(cls, field).offset, key
+    for name in MIRRORED:
+        cls = getattr(sap, name)
+        assert int(out[name]) == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
 
 
 def _cfg(**kw):
@@ -84,6 +87,9 @@ BAD = [
     ("min_len inf", dict(min_len=float("inf")), 1),
     ("close_d nan", dict(close_d=float("nan")), 1),
     ("close_cap<0", dict(close_cap=-5), 1),
+    ("cand_cap<0", dict(cand_cap=-1), 1),
+    ("cand_cap>128", dict(cand_cap=129), 1),
+    ("gemm", dict(gemm=3), 1),
 ]
 
 

@@ -1,15 +1,14 @@
 """GPU parity of the soft-min loss and its hand-written gradient against the
 FP64 oracle, through the C ABI (fused form).
 
-Tolerances follow from the coarse pass's proven bound |r~ - r| <= e_abs +
-e_rel r (reported by sap_info; short pairs are exact FP64):
-  * L is a smooth minimum, so |L~ - L| <= max |r~ - r| <= e_abs + e_rel r_max,
-    plus FP32 rounding of the exponentials and sums (about 1e-5 tau) and of
-    the stored loss (2^-24 |L|);
-  * each gradient term w s c^T / r carries a relative error of at most
-    about (e_abs + e_rel)/tau (through w) + (e_abs + e_rel)/r_min (through 1/r
-    and y_i - y_j), so the gradient is compared in relative Frobenius norm
-    with four times that bound plus 1e-5.
+Bars: |L~ - L| / |L| <= 1e-5 and a relative Frobenius error of the gradient
+<= 1e-4 (FP32 coarse evaluation), each measured error printed per case.  Both
+are also held to the coarse pass's proven bound |r~ - r| <= e_abs + e_rel r
+(sap_info; short pairs are exact FP64): L is a smooth minimum, so
+|L~ - L| <= max |r~ - r|, plus FP32 rounding of the exponentials and sums
+(about 1e-5 tau) and of the stored loss (2^-24 |L|); each gradient term
+w s c^T / r carries a relative error of at most about (e_abs + e_rel)/tau
+(through w) + (e_abs + e_rel)/r_min (through 1/r and y_i - y_j).
 """
 import numpy as np
 import pytest
@@ -26,6 +25,8 @@ if not torch.cuda.is_available():
 from paper_1807_03425_amd import SapContext, SapError, SoftMinSecant  # noqa: E402
 
 DEV = torch.device("cuda:0")
+L_RTOL = 1e-5
+G_RTOL = 1e-4
 
 
 def _ctx(X, P0, **kw):
@@ -54,10 +55,15 @@ def _compare(X, P, tau, tag, min_len=0.0, P_init=None, **kw):
     rmin = oracle.min_secant(X, Pq, min_len=min_len)["r_min"]
     tol_L, tol_G = _tols(ctx.info(), tau, ref["L"], rmin, np.linalg.norm(Pq, 2))
     L = float(loss.item())
-    assert abs(L - ref["L"]) <= tol_L, (tag, L, ref["L"], tol_L)
     G = dP.double().cpu().numpy()
+    eL = abs(L - ref["L"]) / abs(ref["L"])
     rel = np.linalg.norm(G - ref["G"]) / np.linalg.norm(ref["G"])
+    print(f"[softmin] {tag}: L {L:.8g} vs {ref['L']:.8g}: rel err {eL:.2e}; gradient rel err {rel:.2e}",
+          flush=True)
+    assert abs(L - ref["L"]) <= tol_L, (tag, L, ref["L"], tol_L)
     assert rel <= tol_G, (tag, rel, tol_G)
+    assert eL <= L_RTOL, (tag, L, ref["L"], eL)
+    assert rel <= G_RTOL, (tag, rel)
     ctx.close()
     return L, G, ref
 

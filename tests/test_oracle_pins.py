@@ -280,6 +280,33 @@ def test_step_rule_normalized_constant_angle():
         assert abs(sv.min() - np.cos(np.arctan(alpha / (1 - alpha)))) < 1e-13
 
 
+def test_orth_error_flags_non_orthonormal_bases():
+    """The orthonormality checker (the max entry of |P^T P - I|) against
+    values its definition fixes by hand: an off-diagonal defect with unit
+    columns (a diagonal-only check would miss it), a scaled column, a column
+    pair at a known angle, and exactly orthonormal bases (permuted axes, a
+    rotation by a rational-cosine angle)."""
+    n = 5
+    e = np.eye(n)
+    # unit columns at 45 degrees: P^T P = [[1, 1/sqrt2], [1/sqrt2, 1]]
+    P = np.stack([e[0], (e[0] + e[1]) / np.sqrt(2.0)], axis=1)
+    assert abs(oracle.orth_error(P) - 1.0 / np.sqrt(2.0)) < 1e-15
+    # a column of length 2: the diagonal entry 4 - 1 = 3
+    P = np.stack([2.0 * e[0], e[1], e[2]], axis=1)
+    assert oracle.orth_error(P) == 3.0
+    # columns (3, 4)/5 and (4, 3)/5: inner product 24/25
+    P = np.zeros((n, 2))
+    P[0, 0], P[1, 0], P[0, 1], P[1, 1] = 0.6, 0.8, 0.8, 0.6
+    assert abs(oracle.orth_error(P) - 0.96) < 1e-15
+    # a single non-unit column (k = 1): |0.5^2 - 1|
+    assert oracle.orth_error(0.5 * e[:, :1]) == 0.75
+    # exactly orthonormal: permuted axes, and the (3, 4, 5) rotation
+    assert oracle.orth_error(e[:, [3, 0, 4]]) == 0.0
+    P = np.zeros((n, 2))
+    P[1, 0], P[2, 0], P[1, 1], P[2, 1] = 0.6, 0.8, -0.8, 0.6
+    assert oracle.orth_error(P) <= 2.0 ** -52
+
+
 # ---------------------------------------------------------------- loop
 
 def test_run_trace_and_orthonormality():
