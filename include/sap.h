@@ -244,6 +244,67 @@ typedef struct {
 sap_status sap_profile_enable(sap_handle h, int32_t on);
 sap_status sap_profile_read(sap_handle h, sap_profile_t *out);
 
+/* ------------------------------------------------------------------------
+ * Batched SAP: many independent small problems in one launch.
+ *
+ * The paper runs Algorithm 1 on many small secant sets: once per target
+ * dimension to read off the dimension of the data (Sec. 6.1, the sweep over
+ * the projection dimension), on random subsamples of a set too large for its
+ * secant matrix (Sec. 6.3, ten samples of 512 points), and with the length
+ * threshold l of Sec. 7 to see through noise.  sap_batch_run runs B such
+ * problems at once, each on its own workgroup, the whole run of iters
+ * updates and iters+1 evaluations inside one kernel launch.
+ *
+ * A problem is Algorithm 1 on a point set S_s (rows of X listed by
+ * set_points[set_offsets[s] .. set_offsets[s+1]), in that order; pairs and
+ * their tie-break use these local indices) with its own k, alpha, rule and
+ * start P0_b.  The set's threshold set_min_len[s] drops secants shorter than
+ * l (Sec. 7) and duplicates.  Evaluation: Y = (X_S - mean) P in FP64 on the
+ * matrix cores, coarse values ||y_i - y_j||^2 / d^2 rounded to FP32, and
+ * FP64 rescoring from X of every pair in the proven window, as in the
+ * single-problem handle (so there is no short-pair list); the update is the
+ * handle's FP64 update.  Results are those of an FP64 evaluation whenever a
+ * trace entry is certified.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t set;        /* its point set, 0 .. n_sets - 1                     */
+    int32_t k;          /* target dimension, 1 .. min(n, 16)                  */
+    int32_t rule;       /* SAP_STEP_LITERAL | SAP_STEP_NORMALIZED             */
+    int32_t reserved;   /* 0                                                  */
+    double alpha;       /* shift, in [0, 1]                                   */
+} sap_batch_problem;
+
+typedef struct {
+    double init_ms;     /* device time of the per-set precomputation          */
+    double run_ms;      /* device time of the run kernel (all problems)      */
+    int64_t n_pairs;    /* kept pairs summed over the problems' sets          */
+    int64_t scratch_bytes; /* device scratch the call used                    */
+} sap_batch_stats;
+
+/* Run the batch.  Host arrays: set_offsets (n_sets + 1, increasing, sets of
+ * 2 .. 32768 points), set_points (set_offsets[n_sets] row indices into X,
+ * each in [0, N)), set_min_len (n_sets, finite, >= 0; may be NULL = all 0),
+ * problems (n_problems).  Device arrays: X (N x n, row-major, ldx >= n, FP64
+ * or FP32, finite), P0 and P_out (problem b's n x k_b row-major block at
+ * offset n * sum_{a<b} k_a doubles; every P0 block orthonormal to 1e-6),
+ * min_trace (n_problems x (iters + 1) FP64: entry [b][it] is the minimum at
+ * the it-th evaluation), ij_trace (n_problems x (iters + 1) x 2 int64, local
+ * indices; may be NULL), cert_trace (n_problems x (iters + 1) int32; may be
+ * NULL).  A set without any kept pair gives min = +inf, (-1, -1),
+ * certified = 0, and P unchanged.  Limits: n * (k + 2) <= 16384 per problem
+ * (the update's vectors live in LDS).  cand_cap as in sap_config (0 = 128).
+ * stats may be NULL.  The call allocates its device scratch, synchronises
+ * the stream, and frees the scratch before it returns.  Errors:
+ * SAP_ERR_INVALID_ARG, SAP_ERR_NONFINITE, SAP_ERR_NOT_ORTHONORMAL,
+ * SAP_ERR_UNSUPPORTED, SAP_ERR_OUT_OF_MEMORY, SAP_ERR_DEVICE; the message is
+ * sap_last_error(NULL). */
+sap_status sap_batch_run(const void *X, int32_t dtype, int64_t N, int32_t n, int64_t ldx,
+                         int32_t n_sets, const int64_t *set_offsets, const int32_t *set_points,
+                         const double *set_min_len, int32_t n_problems,
+                         const sap_batch_problem *problems, const double *P0, int32_t iters,
+                         int32_t cand_cap, double *P_out, double *min_trace, int64_t *ij_trace,
+                         int32_t *cert_trace, void *stream, sap_batch_stats *stats);
+
 /* Free everything the handle owns.  NULL is accepted. */
 sap_status sap_destroy(sap_handle h);
 

@@ -64,6 +64,16 @@ class sap_profile_t(C.Structure):
     _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
 
 
+class sap_batch_problem(C.Structure):
+    _fields_ = [("set", C.c_int32), ("k", C.c_int32), ("rule", C.c_int32),
+                ("reserved", C.c_int32), ("alpha", C.c_double)]
+
+
+class sap_batch_stats(C.Structure):
+    _fields_ = [("init_ms", C.c_double), ("run_ms", C.c_double), ("n_pairs", C.c_int64),
+                ("scratch_bytes", C.c_int64)]
+
+
 PROFILE_SLOTS = ("gemm", "pass", "select", "sm_fwd", "sm_bwd", "sm_other", "select_gemm")
 
 _lib: Optional[C.CDLL] = None
@@ -83,6 +93,10 @@ _SIGS = {
     "sap_softmin_bwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
     "sap_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "sap_profile_read": (C.c_int, [C.c_void_p, C.POINTER(sap_profile_t)]),
+    "sap_batch_run": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int32, C.c_int64, C.c_int32,
+                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.POINTER(sap_batch_stats)]),
     "sap_destroy": (C.c_int, [C.c_void_p]),
     "sap_last_error": (C.c_char_p, [C.c_void_p]),
 }
@@ -267,6 +281,63 @@ class SapContext:
         return dP
 
 
+def batch_run(X, sets, problems, P0s, iters: int, set_min_len=None, cand_cap: int = 0,
+              stream=None, noalloc: bool = False) -> dict:
+    """Run independent SAP problems on point subsets of X in one launch
+    (sap_batch_run).
+
+    X: N x n cuda tensor (float32/float64, unit stride along n).
+    sets: list of 1-D integer index arrays (rows of X; the order defines the
+        local indices of each set's pairs).
+    problems: list of dicts with keys set, k, and optionally alpha (0.01),
+        rule ("literal" | "normalized").
+    P0s: list of n x k_b starting projections (one per problem).
+    Returns dict(min=(B, iters+1) float64, ij=(B, iters+1, 2) int64,
+    certified=(B, iters+1) int32 device tensors, P=[n x k_b float64 device
+    tensors], stats=dict)."""
+    import numpy as np
+    import torch
+    if X.dim() != 2 or X.device.type != "cuda" or X.stride(1) != 1:
+        raise ValueError("X must be a 2-D cuda tensor with unit stride along n")
+    if X.dtype not in (torch.float32, torch.float64):
+        raise ValueError("X must be float32 or float64")
+    dev = X.device
+    N, n = X.shape
+    offs = np.zeros(len(sets) + 1, dtype=np.int64)
+    for s_i, ix in enumerate(sets):
+        offs[s_i + 1] = offs[s_i] + len(ix)
+    pts = np.ascontiguousarray(np.concatenate([np.asarray(ix, dtype=np.int32) for ix in sets]))
+    ml = None if set_min_len is None else np.ascontiguousarray(set_min_len, dtype=np.float64)
+    B = len(problems)
+    probs = (sap_batch_problem * B)()
+    ks = []
+    for b, q in enumerate(problems):
+        rule = {"literal": SAP_STEP_LITERAL, "normalized": SAP_STEP_NORMALIZED}[q.get("rule", "literal")]
+        probs[b] = sap_batch_problem(int(q["set"]), int(q["k"]), rule, 0, float(q.get("alpha", 0.01)))
+        ks.append(int(q["k"]))
+    P0 = torch.cat([torch.as_tensor(P).to(device=dev, dtype=torch.float64).reshape(-1) for P in P0s]).contiguous()
+    P_out = torch.empty_like(P0)
+    m = iters + 1
+    tmin = torch.empty((B, m), dtype=torch.float64, device=dev)
+    tij = torch.empty((B, m, 2), dtype=torch.int64, device=dev)
+    tcert = torch.empty((B, m), dtype=torch.int32, device=dev)
+    st = sap_batch_stats()
+    fn = lib().sap_batch_run_noalloc if noalloc else lib().sap_batch_run
+    rc = fn(_dptr(X), SAP_F64 if X.dtype == torch.float64 else SAP_F32, N, n, X.stride(0),
+            len(sets), offs.ctypes.data_as(C.c_void_p), pts.ctypes.data_as(C.c_void_p),
+            ml.ctypes.data_as(C.c_void_p) if ml is not None else None, B, probs, _dptr(P0),
+            int(iters), int(cand_cap), _dptr(P_out), _dptr(tmin), _dptr(tij), _dptr(tcert),
+            _stream_ptr(stream), C.byref(st))
+    _check(rc, None)
+    Ps, off = [], 0
+    for k in ks:
+        Ps.append(P_out[off:off + n * k].reshape(n, k))
+        off += n * k
+    return dict(min=tmin, ij=tij, certified=tcert, P=Ps,
+                stats=dict(init_ms=st.init_ms, run_ms=st.run_ms, n_pairs=st.n_pairs,
+                           scratch_bytes=st.scratch_bytes))
+
+
 def _make_softmin_function():
     import torch
 
@@ -308,4 +379,5 @@ class _LazySoftMin:
 SoftMinSecant = _LazySoftMin()
 
 __all__ = ["SapContext", "SoftMinSecant", "SapError", "lib", "LIB_PATH", "sap_config",
-           "sap_min_result", "sap_info_t", "sap_profile_t"]
+           "sap_min_result", "sap_info_t", "sap_profile_t", "sap_batch_problem", "sap_batch_stats",
+           "batch_run"]

@@ -1,8 +1,9 @@
 """Build the HIP library libsap.so for gfx950 (in-tree, next to this file).
 
 The host runtime and the K-independent kernels form one translation unit
-(csrc/sap_api.hip); the kernels templated on the projection width K are
-compiled once per K = 1..16 from csrc/sap_kinst.hip.  The units compile in
+(csrc/sap_api.hip), the batched engine another (csrc/sap_batch.hip); the
+kernels templated on the projection width K are compiled once per K = 1..16
+from csrc/sap_kinst.hip.  The units compile in
 parallel to objects under _build/ and are linked into one shared library.
 """
 from __future__ import annotations
@@ -36,7 +37,8 @@ def sources() -> list[Path]:
 
 
 def _units() -> list[tuple[Path, list[str], Path]]:
-    units = [(CSRC / "sap_api.hip", [], OBJ / "sap_api.o")]
+    units = [(CSRC / "sap_api.hip", [], OBJ / "sap_api.o"),
+             (CSRC / "sap_batch.hip", [], OBJ / "sap_batch.o")]
     for k in range(1, KMAX + 1):
         units.append((CSRC / "sap_kinst.hip", [f"-DSAP_K={k}"], OBJ / f"sap_k{k}.o"))
     return units

@@ -107,6 +107,8 @@ struct sap_ctx {
 
 static thread_local std::string g_tls_err;
 
+void sap_internal_set_error(const char *msg) { g_tls_err = msg; }
+
 static sap_status fail(sap_ctx *h, sap_status st, const char *fmt, ...) {
     char buf[512];
     va_list ap;

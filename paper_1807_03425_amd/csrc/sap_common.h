@@ -140,6 +140,10 @@ struct LaunchCfg {
 
 }  // namespace sap
 
+// Record the calling thread's last error (the message sap_last_error(NULL)
+// returns); defined in the host runtime, used by every entry point.
+void sap_internal_set_error(const char *msg);
+
 // Dispatch a templated launch over the projection width K = 1..16.
 #define SAP_DISPATCH_K(kval, ...)                                           \
     switch (kval) {                                                          \

@@ -34,7 +34,8 @@ import numpy as np
 
 __all__ = [
     "Workload", "random_orthonormal", "trig_curve", "rotated_blob",
-    "hyperspectral", "gaussian_torus", "make", "WORKLOADS",
+    "hyperspectral", "gaussian_torus", "embedded_manifold", "subsample_sets",
+    "sweep_starts", "make", "WORKLOADS",
 ]
 
 
@@ -143,6 +144,54 @@ def gaussian_torus(N: int, seed: int, k: int = 16, dim: int = 8, n: int = 256,
     X = Z @ Q.T
     P0 = random_orthonormal(rp, n, k)
     return np.ascontiguousarray(X.astype(np.float32)), P0
+
+
+def embedded_manifold(kind: str, N: int, seed: int, n: int = 15,
+                      quad: float = 0.5) -> np.ndarray:
+    """Points sampled uniformly from a small manifold and smoothly embedded
+    into R^n (the sweep of the paper's Sec. 6.1, whose embedding is not
+    stated): base points z of
+      "curve"  -- t -> (cos t, sin t, cos 2t), t ~ U[0, 2pi)        (R^3)
+      "torus"  -- the torus of radii 2 and 1 in R^3, angles uniform  (R^3)
+      "sphere" -- the unit 3-sphere in R^4, normalised Gaussians     (R^4)
+    are mapped to [z, quad * (z_a z_b)_{a <= b}] (a smooth, non-linear
+    embedding), zero-padded to R^n and rotated by a Haar orthogonal matrix.
+    FP64."""
+    rd = np.random.default_rng(np.random.SeedSequence(seed).spawn(2)[0])
+    if kind == "curve":
+        t = rd.uniform(0.0, 2.0 * np.pi, size=N)
+        Z = np.stack([np.cos(t), np.sin(t), np.cos(2 * t)], axis=1)
+    elif kind == "torus":
+        u = rd.uniform(0.0, 2.0 * np.pi, size=N)
+        v = rd.uniform(0.0, 2.0 * np.pi, size=N)
+        Z = np.stack([(2.0 + np.cos(v)) * np.cos(u), (2.0 + np.cos(v)) * np.sin(u), np.sin(v)], axis=1)
+    elif kind == "sphere":
+        G = rd.standard_normal((N, 4))
+        Z = G / np.linalg.norm(G, axis=1, keepdims=True)
+    else:
+        raise KeyError(kind)
+    d = Z.shape[1]
+    quads = [Z[:, a] * Z[:, b] for a in range(d) for b in range(a, d)]
+    F = np.concatenate([Z, quad * np.stack(quads, axis=1)], axis=1)
+    if F.shape[1] > n:
+        raise ValueError("embedding dimension too small")
+    E = np.zeros((N, n))
+    E[:, :F.shape[1]] = F
+    Q = random_orthonormal(rd, n, n)
+    return np.ascontiguousarray(E @ Q.T)
+
+
+def subsample_sets(N: int, count: int, size: int, seed: int) -> list:
+    """`count` random subsets of `size` distinct rows of an N-point set (the
+    sampling of the paper's Sec. 6.3), each in increasing row order."""
+    rd = np.random.default_rng(seed)
+    return [np.sort(rd.choice(N, size=size, replace=False)).astype(np.int32) for _ in range(count)]
+
+
+def sweep_starts(n: int, ks, seed: int) -> list:
+    """One seeded random orthonormal n x k start per k of a sweep."""
+    rp = np.random.default_rng(seed)
+    return [random_orthonormal(rp, n, int(k)) for k in ks]
 
 
 def make(name: str, N: Optional[int] = None, k: Optional[int] = None,

@@ -29,7 +29,8 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(sap._SIGS)
 
 
-MIRRORED = ("sap_config", "sap_min_result", "sap_info_t", "sap_profile_t")
+MIRRORED = ("sap_config", "sap_min_result", "sap_info_t", "sap_profile_t", "sap_batch_problem",
+            "sap_batch_stats")
 
 
 def test_struct_layout_matches_header(tmp_path):
@@ -124,3 +125,36 @@ def test_null_handle_calls_fail_cleanly():
     assert L.sap_step(None, None) == 1
     assert L.sap_run(None, 3, None, None, None) == 1
     assert L.sap_destroy(None) == 0
+
+
+def _batch_call(**kw):
+    """sap_batch_run with fake device pointers: argument validation comes
+    before any device call."""
+    import numpy as np
+    L = sap.lib()
+    fake = C.c_void_p(0x1000)
+    offs = np.array(kw.get("offs", [0, 3]), dtype=np.int64)
+    pts = np.array(kw.get("pts", [0, 1, 2]), dtype=np.int32)
+    probs = (sap.sap_batch_problem * 1)(sap.sap_batch_problem(kw.get("set", 0), kw.get("k", 2), kw.get("rule", 0),
+                                                             0, kw.get("alpha", 0.01)))
+    ml = np.array(kw.get("ml", [0.0]), dtype=np.float64)
+    return L.sap_batch_run(fake, kw.get("dtype", sap.SAP_F64), kw.get("N", 10), kw.get("n", 4),
+                           kw.get("ldx", 4), len(offs) - 1, offs.ctypes.data_as(C.c_void_p),
+                           pts.ctypes.data_as(C.c_void_p), ml.ctypes.data_as(C.c_void_p), 1, probs,
+                           fake, kw.get("iters", 1), kw.get("cap", 0), fake, fake, None, None, None, None)
+
+
+BATCH_BAD = [
+    ("dtype", dict(dtype=5), 1), ("N<2", dict(N=1), 1), ("n<1", dict(n=0), 1), ("ldx<n", dict(ldx=3), 1),
+    ("iters<0", dict(iters=-1), 1), ("cap", dict(cap=200), 1), ("offs0", dict(offs=[1, 3]), 1),
+    ("set of 1", dict(offs=[0, 1], pts=[0]), 1), ("point outside X", dict(pts=[0, 1, 10]), 1),
+    ("min_len<0", dict(ml=[-1.0]), 1), ("set index", dict(set=1), 1), ("k>n", dict(k=5), 1),
+    ("k<1", dict(k=0), 1), ("alpha", dict(alpha=2.0), 1), ("rule", dict(rule=3), 1),
+    ("k>16", dict(n=40, ldx=40, k=17), 8), ("lds", dict(n=2000, ldx=2000, k=8), 8),
+]
+
+
+@pytest.mark.parametrize("name,kw,status", BATCH_BAD, ids=[b[0] for b in BATCH_BAD])
+def test_batch_rejects_bad_arguments_before_any_device_call(name, kw, status):
+    assert _batch_call(**kw) == status, (name, sap.lib().sap_last_error(None))
+    assert sap.lib().sap_last_error(None)
