@@ -305,6 +305,25 @@ sap_status sap_batch_run(const void *X, int32_t dtype, int64_t N, int32_t n, int
                          int32_t cand_cap, double *P_out, double *min_trace, int64_t *ij_trace,
                          int32_t *cert_trace, void *stream, sap_batch_stats *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as sap_batch_run -- same arguments, same kernels, same results --
+ * except that its device scratch is a fixed array inside the library, 32 MiB
+ * per GPU (each GPU the library runs on holds it until the process ends),
+ * and that it creates no events (stats, if given, reports init_ms = run_ms =
+ * -1).  It calls no hipMalloc or hipFree.  A batch that needs more scratch
+ * than the array holds (stats->scratch_bytes of sap_batch_run tells) fails
+ * with SAP_ERR_CAPACITY.  Every call on a GPU uses that GPU's one array and
+ * leaves its contents behind (each call rewrites what it reads, and clears
+ * its counters with a kernel): calls that overlap on one GPU (concurrent
+ * streams or threads) race, and must be serialised by the caller. */
+sap_status sap_batch_run_noalloc(const void *X, int32_t dtype, int64_t N, int32_t n, int64_t ldx,
+                                 int32_t n_sets, const int64_t *set_offsets, const int32_t *set_points,
+                                 const double *set_min_len, int32_t n_problems,
+                                 const sap_batch_problem *problems, const double *P0, int32_t iters,
+                                 int32_t cand_cap, double *P_out, double *min_trace, int64_t *ij_trace,
+                                 int32_t *cert_trace, void *stream, sap_batch_stats *stats);
+
 /* Free everything the handle owns.  NULL is accepted. */
 sap_status sap_destroy(sap_handle h);
 

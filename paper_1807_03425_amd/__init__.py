@@ -97,6 +97,10 @@ _SIGS = {
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                 C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.POINTER(sap_batch_stats)]),
+    "sap_batch_run_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int32, C.c_int64, C.c_int32,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                        C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(sap_batch_stats)]),
     "sap_destroy": (C.c_int, [C.c_void_p]),
     "sap_last_error": (C.c_char_p, [C.c_void_p]),
 }

@@ -33,6 +33,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -640,7 +641,7 @@ sap_status check_P0(const BatchPlan &pl, int n, const double *P0, hipStream_t st
 sap_status run_batch(const BatchPlan &pl, char *base, const void *X, int32_t dtype, int64_t ldx, int32_t n,
                      int32_t n_sets, int32_t n_problems, const double *P0, int32_t iters, int32_t cand_cap,
                      double *P_out, double *min_trace, int64_t *ij_trace, int32_t *cert_trace, hipStream_t stream,
-                     sap_batch_stats *stats) {
+                     sap_batch_stats *stats, bool timed) {
     BatchArgs a{};
     a.X = X;
     a.ldx = ldx;
@@ -672,7 +673,7 @@ sap_status run_batch(const BatchPlan &pl, char *base, const void *X, int32_t dty
     B_HIP(hipMemcpyAsync(base + pl.o_minlen, pl.minlen.data(), sizeof(double) * pl.minlen.size(), hipMemcpyHostToDevice,
                          stream));
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-    if (stats) {
+    if (timed) {
         B_HIP(hipEventCreate(&e0));
         B_HIP(hipEventCreate(&e1));
         B_HIP(hipEventCreate(&e2));
@@ -717,7 +718,7 @@ sap_status run_batch(const BatchPlan &pl, char *base, const void *X, int32_t dty
         for (const BatchProb &p : pl.probs) kept += (int64_t)hs[p.set].kept;
         if (stats) stats->n_pairs = kept;
     }
-    if (stats) B_HIP(hipEventRecord(e1, stream));
+    if (timed) B_HIP(hipEventRecord(e1, stream));
     const void *fn = dtype == SAP_F64 ? reinterpret_cast<const void *>(&k_batch_run<double>)
                                       : reinterpret_cast<const void *>(&k_batch_run<float>);
     B_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds));
@@ -726,18 +727,22 @@ sap_status run_batch(const BatchPlan &pl, char *base, const void *X, int32_t dty
     else
         hipLaunchKernelGGL(k_batch_run<float>, dim3((unsigned)n_problems), dim3(kPairBlock), (uint32_t)pl.lds, stream, a);
     if ((st = launched("k_batch_run")) != SAP_OK) return st;
-    if (stats) B_HIP(hipEventRecord(e2, stream));
+    if (timed) B_HIP(hipEventRecord(e2, stream));
     hipLaunchKernelGGL(k_batch_storeP, dim3((unsigned)((kpmax * n + 255) / 256), (unsigned)n_problems), dim3(256), 0,
                        stream, a);
     if ((st = launched("k_batch_storeP")) != SAP_OK) return st;
     B_HIP(hipStreamSynchronize(stream));
     if (stats) {
+        stats->init_ms = -1.0;
+        stats->run_ms = -1.0;
+        stats->scratch_bytes = (int64_t)pl.total;
+    }
+    if (timed) {
         float t1 = 0.0f, t2 = 0.0f;
         B_HIP(hipEventElapsedTime(&t1, e0, e1));
         B_HIP(hipEventElapsedTime(&t2, e1, e2));
         stats->init_ms = t1;
         stats->run_ms = t2;
-        stats->scratch_bytes = (int64_t)pl.total;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         (void)hipEventDestroy(e2);
@@ -767,8 +772,64 @@ extern "C" sap_status sap_batch_run(const void *X, int32_t dtype, int64_t N, int
                      pl.total, hipGetErrorString(e));
     }
     st = run_batch(pl, static_cast<char *>(base), X, dtype, ldx, n, n_sets, n_problems, P0, iters, cand_cap, P_out,
-                   min_trace, ij_trace, cert_trace, s, stats);
+                   min_trace, ij_trace, cert_trace, s, stats, stats != nullptr);
     (void)hipStreamSynchronize(s);
     (void)hipFree(base);
+    return st;
+}
+
+// ---------------------------------------------------------------- allocation-free variant
+
+// The scratch of sap_batch_run_noalloc: a fixed array in device memory.  In
+// host code its name only stands for the symbol; its address on a device is
+// looked up once per device (hipGetSymbolAddress, with that device current)
+// and that address is what the kernels are given.  Each device holds its own
+// copy until the process ends; every call on one device shares it.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<char *> g_scratch_ptr;   // per device id: the array's device address
+
+sap_status static_scratch(char **out) {
+    int dev = 0;
+    B_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch_ptr[(size_t)dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return bfail(SAP_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        }
+        g_scratch_ptr[(size_t)dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_ptr[(size_t)dev];
+    return SAP_OK;
+}
+}  // namespace
+
+extern "C" sap_status sap_batch_run_noalloc(const void *X, int32_t dtype, int64_t N, int32_t n, int64_t ldx,
+                                            int32_t n_sets, const int64_t *set_offsets, const int32_t *set_points,
+                                            const double *set_min_len, int32_t n_problems,
+                                            const sap_batch_problem *problems, const double *P0, int32_t iters,
+                                            int32_t cand_cap, double *P_out, double *min_trace, int64_t *ij_trace,
+                                            int32_t *cert_trace, void *stream, sap_batch_stats *stats) {
+    BatchPlan pl;
+    sap_status st = plan_batch(X, dtype, N, n, ldx, n_sets, set_offsets, set_points, set_min_len, n_problems, problems,
+                               P0, iters, cand_cap, P_out, min_trace, pl);
+    if (st != SAP_OK) return st;
+    if (pl.total > kStaticScratchBytes)
+        return bfail(SAP_ERR_CAPACITY, "sap_batch_run_noalloc: the batch needs %zu bytes of scratch, above the fixed %zu",
+                     pl.total, kStaticScratchBytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = nullptr;
+    if ((st = static_scratch(&base)) != SAP_OK) return st;
+    if ((st = check_P0(pl, n, P0, s)) != SAP_OK) return st;
+    st = run_batch(pl, base, X, dtype, ldx, n, n_sets, n_problems, P0, iters, cand_cap, P_out, min_trace, ij_trace,
+                   cert_trace, s, stats, false);
+    (void)hipStreamSynchronize(s);
     return st;
 }
