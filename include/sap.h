@@ -186,6 +186,31 @@ sap_status sap_run(sap_handle h, int32_t iters, double *min_trace,
 sap_status sap_get_P(sap_handle h, double *P_out);
 sap_status sap_set_P(sap_handle h, const double *P);
 
+/* Algorithm 1's initial projection (Sec. 4; Algorithm 1, step 2): P(1) =
+ * the first k columns of U, where S = U Sigma V^T is the SVD of the secant
+ * matrix S (the handle's kept unit secants as columns) -- the top-k
+ * eigenvectors of S S^T = sum_{kept i<j} s_ij s_ij^T.  Computed on the device
+ * in FP64 without forming S: S S^T = sum_i (x_i - mean) z_i^T with
+ * z_i = sum_j (x_i - x_j) / d_ij^2 (direct differences), then a subspace
+ * iteration with Rayleigh-Ritz until the largest residual
+ * ||S S^T p_c - sigma_c^2 p_c|| / sigma_1^2 of the k vectors is <= 1e-12 (at
+ * most 400 rounds).  Each column is signed so that its largest-magnitude
+ * component is positive (the first such component on ties).  Writes P
+ * (n x k row-major device buffer; may be NULL) and info (host; may be
+ * NULL); with set_P != 0 the result also becomes the handle's current P.
+ * Device scratch of about 4 N^2 + 8 N n + 16 n^2 bytes is allocated and
+ * freed by the call, which synchronises.  Errors: SAP_ERR_INVALID_ARG,
+ * SAP_ERR_OUT_OF_MEMORY, SAP_ERR_DEVICE. */
+typedef struct {
+    double sigma[16];     /* the k largest singular values of S, descending; 0 beyond k */
+    double residual;      /* max over the k vectors of the relative residual above     */
+    double ms;            /* device time of the whole computation                     */
+    int32_t iters;        /* rounds of the subspace iteration                         */
+    int32_t converged;    /* 1 when residual <= 1e-12                                 */
+} sap_pca_info;
+
+sap_status sap_pca_init(sap_handle h, double *P_out, sap_pca_info *info, int32_t set_P);
+
 /* Change the stream later work is enqueued on (no device work). */
 sap_status sap_set_stream(sap_handle h, void *stream);
 

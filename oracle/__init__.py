@@ -67,6 +67,8 @@ def _load():
         lib.oracle_run.argtypes = [p, i64, i32, p, i32, d, d, i32, i32, p, p, p, p, p]
         lib.oracle_softmin.argtypes = [p, i64, i32, p, i32, d, d, C.POINTER(d), p,
                                        C.POINTER(d), C.POINTER(i64), C.POINTER(i64)]
+        lib.oracle_secant_matrix.argtypes = [p, i64, i32, d, p, i64]
+        lib.oracle_secant_matrix.restype = i64
         lib.oracle_unit_secant.argtypes = [p, i64, i32, i64, i64, p]
         lib.oracle_unit_secant.restype = d
         lib.oracle_pair_index.argtypes = [i64, i64, i64]
@@ -211,3 +213,34 @@ def softmin(X, P, tau: float, min_len: float = 0.0, grad: bool = True) -> dict:
     _check(st, "softmin")
     return dict(L=L.value, G=G, wsum=wsum.value, n_pairs=npairs.value,
                 n_zero=nzero.value)
+
+
+def secant_matrix(X, min_len: float = 0.0) -> np.ndarray:
+    """S (n x |Pi|): the kept unit secants as columns, in pair-index order
+    (Sec. 4, the secant matrix whose SVD initialises Algorithm 1)."""
+    X = _X(X)
+    N, n = X.shape
+    cap = N * (N - 1) // 2
+    S = np.empty((cap, n))
+    q = _load().oracle_secant_matrix(_ptr(X), N, n, float(min_len), _ptr(S), cap)
+    if q < 0:
+        raise OracleError("secant_matrix: bad arguments")
+    return np.ascontiguousarray(S[:q].T)
+
+
+def pca_init(X, k: int, min_len: float = 0.0) -> tuple[np.ndarray, np.ndarray]:
+    """Algorithm 1's initial projection (Sec. 4): the first k columns of U in
+    S = U Sigma V^T, with S the explicit secant matrix.  Returns (P, sigma):
+    P n x k with each column's largest-magnitude component positive (the
+    first such component on ties), sigma the k largest singular values; the
+    third value is every singular value.  The SVD is the library routine
+    (numpy / LAPACK)."""
+    S = secant_matrix(X, min_len)
+    U, sv, _ = np.linalg.svd(S, full_matrices=False)
+    P = U[:, :k].copy()
+    for c in range(k):
+        t = int(np.argmax(np.abs(P[:, c])))
+        if P[t, c] < 0:
+            P[:, c] = -P[:, c]
+    return P, sv[:k].copy(), sv
+

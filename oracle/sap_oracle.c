@@ -435,6 +435,25 @@ done:
     return st;
 }
 
+/* The secant matrix S of Sec. 4: every kept unit secant as a column (pairs
+ * in pair-index order; dropped pairs -- duplicates, d < min_len -- are left
+ * out).  S is n x cap, column-major (column q at S + q*n).  Returns the
+ * number of columns written, or -1 if cap is too small or an argument is
+ * bad. */
+int64_t oracle_secant_matrix(const double *X, int64_t N, int32_t n, double min_len,
+                             double *S, int64_t cap) {
+    if (!X || !S || N < 2 || n < 1 || min_len < 0) return -1;
+    int64_t q = 0;
+    for (int64_t i = 0; i < N - 1; ++i)
+        for (int64_t j = i + 1; j < N; ++j) {
+            if (q >= cap) return -1;
+            double d = unit_secant(X, n, i, j, S + (size_t)q * n);
+            if (d == 0.0 || d < min_len) continue;   /* the column is overwritten next */
+            ++q;
+        }
+    return q;
+}
+
 /* Kahan-compensated running sum */
 typedef struct { double s, c; } ksum_t;
 static void kadd(ksum_t *k, double x) {

@@ -64,6 +64,11 @@ class sap_profile_t(C.Structure):
     _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
 
 
+class sap_pca_info(C.Structure):
+    _fields_ = [("sigma", C.c_double * 16), ("residual", C.c_double), ("ms", C.c_double),
+                ("iters", C.c_int32), ("converged", C.c_int32)]
+
+
 class sap_batch_problem(C.Structure):
     _fields_ = [("set", C.c_int32), ("k", C.c_int32), ("rule", C.c_int32),
                 ("reserved", C.c_int32), ("alpha", C.c_double)]
@@ -88,6 +93,7 @@ _SIGS = {
     "sap_get_P": (C.c_int, [C.c_void_p, C.c_void_p]),
     "sap_set_P": (C.c_int, [C.c_void_p, C.c_void_p]),
     "sap_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sap_pca_init": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(sap_pca_info), C.c_int32]),
     "sap_info": (C.c_int, [C.c_void_p, C.POINTER(sap_info_t)]),
     "sap_softmin_fwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
     "sap_softmin_bwd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
@@ -243,6 +249,17 @@ class SapContext:
         P = P.to(device=self._X.device, dtype=torch.float64).contiguous()
         _check(lib().sap_set_P(self.handle, _dptr(P)), self.handle)
 
+    def pca_init(self, set_P: bool = False):
+        """Algorithm 1's initial projection: the top-k left singular vectors
+        of the secant matrix (sap_pca_init).  Returns (P n x k float64 cuda
+        tensor, info dict); with set_P it also becomes the current P."""
+        import torch
+        P = torch.empty((self.n, self.k), dtype=torch.float64, device=self._X.device)
+        info = sap_pca_info()
+        _check(lib().sap_pca_init(self.handle, _dptr(P), C.byref(info), 1 if set_P else 0), self.handle)
+        return P, dict(sigma=list(info.sigma)[:self.k], residual=info.residual, ms=info.ms,
+                       iters=info.iters, converged=info.converged)
+
     def set_stream(self, stream):
         self._stream = stream
         _check(lib().sap_set_stream(self.handle, _stream_ptr(stream)), self.handle)
@@ -384,4 +401,5 @@ SoftMinSecant = _LazySoftMin()
 
 __all__ = ["SapContext", "SoftMinSecant", "SapError", "lib", "LIB_PATH", "sap_config",
            "sap_min_result", "sap_info_t", "sap_profile_t", "sap_batch_problem", "sap_batch_stats",
+           "sap_pca_info",
            "batch_run"]

@@ -20,6 +20,7 @@
 #include "sap_init.hip"
 #include "sap_iter.hip"
 #include "sap_softmin.hip"
+#include "sap_pca.hip"
 #include "sap_launch.h"
 
 using namespace sap;
@@ -766,7 +767,106 @@ static sap_status sm_backward(sap_ctx *h, double tau, const float *grad_loss, fl
     return SAP_OK;
 }
 
-// ---------------------------------------------------------------- C ABI
+// ---------------------------------------------------------------- secant-PCA start
+
+// Scratch of one PCA computation, freed on every exit path.
+struct PcaScratch {
+    std::vector<void *> ptrs;
+    ~PcaScratch() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <typename T>
+    hipError_t get(T **out, size_t bytes) {
+        void *p = nullptr;
+        const hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
+        if (e == hipSuccess) ptrs.push_back(p);
+        *out = static_cast<T *>(p);
+        return e;
+    }
+};
+
+template <typename TX>
+static sap_status pca_run(sap_ctx *h, double *P_out, sap_pca_info *info, bool set_P) {
+    const int n = h->n, k = h->k;
+    const int64_t N = h->N, nb = ceil_div(N, kTile), ntiles = nb * (nb + 1) / 2;
+    const int b = std::min(n, std::min(kPcaMaxB, std::max(k + 8, 2 * k)));
+    const TX *X = static_cast<const TX *>(h->X);
+    PcaScratch sc;
+    int2 *d_tiles = nullptr;
+    double *W = nullptr, *Z = nullptr, *Cm = nullptr, *Cs = nullptr, *V = nullptr, *T = nullptr, *out = nullptr,
+           *P = nullptr;
+    SAP_HIP(h, sc.get(&d_tiles, sizeof(int2) * ntiles));
+    SAP_HIP(h, sc.get(&W, sizeof(double) * (size_t)ntiles * kTileElems));
+    SAP_HIP(h, sc.get(&Z, sizeof(double) * (size_t)N * n));
+    SAP_HIP(h, sc.get(&Cm, sizeof(double) * (size_t)n * n));
+    SAP_HIP(h, sc.get(&Cs, sizeof(double) * (size_t)n * n));
+    SAP_HIP(h, sc.get(&V, sizeof(double) * (size_t)n * b));
+    SAP_HIP(h, sc.get(&T, sizeof(double) * (size_t)n * b));
+    SAP_HIP(h, sc.get(&out, sizeof(double) * (kPcaMaxB + 1)));
+    SAP_HIP(h, sc.get(&P, sizeof(double) * (size_t)n * k));
+    std::vector<int2> tiles((size_t)ntiles);
+    for (int64_t bi = 0, t = 0; bi < nb; ++bi)
+        for (int64_t bj = bi; bj < nb; ++bj, ++t) tiles[(size_t)t] = make_int2((int)bi, (int)bj);
+    SAP_HIP(h, hipMemcpyAsync(d_tiles, tiles.data(), sizeof(int2) * ntiles, hipMemcpyHostToDevice, h->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SAP_HIP(h, hipEventCreate(&e0));
+    SAP_HIP(h, hipEventCreate(&e1));
+    SAP_HIP(h, hipEventRecord(e0, h->stream));
+    const unsigned gw = (unsigned)std::min<int64_t>(ntiles, 8192);
+    hipLaunchKernelGGL(k_pca_w<TX>, dim3(gw), dim3(256), 0, h->stream, X, h->ldx, N, n, d_tiles, ntiles,
+                       h->cfg.min_len, W);
+    SAP_LAUNCHED(h, "k_pca_w");
+    hipLaunchKernelGGL(k_pca_z<TX>, dim3((unsigned)nb, (unsigned)ceil_div(n, kTile)), dim3(256), 0, h->stream, X,
+                       h->ldx, N, n, nb, (const double *)W, Z);
+    SAP_LAUNCHED(h, "k_pca_z");
+    const unsigned gn = (unsigned)ceil_div(n, kTile);
+    hipLaunchKernelGGL(k_pca_gram<TX>, dim3(gn, gn), dim3(256), 0, h->stream, X, h->ldx, N, n,
+                       (const double *)h->d_mu, (const double *)Z, Cm);
+    SAP_LAUNCHED(h, "k_pca_gram");
+    hipLaunchKernelGGL(k_pca_sym, dim3((unsigned)ceil_div((int64_t)n * n, 256)), dim3(256), 0, h->stream,
+                       (const double *)Cm, n, Cs);
+    SAP_LAUNCHED(h, "k_pca_sym");
+    const dim3 gmv((unsigned)ceil_div((int64_t)n * b, 256));
+    hipLaunchKernelGGL(k_pca_start, gmv, dim3(256), 0, h->stream, V, n, b);
+    hipLaunchKernelGGL(k_pca_orth, dim3(1), dim3(256), 0, h->stream, V, n, b, 0);
+    SAP_LAUNCHED(h, "k_pca_orth");
+    double hout[kPcaMaxB + 1] = {0};
+    int it = 0;
+    bool conv = false;
+    for (it = 1; it <= 400; ++it) {
+        // two power steps, orthonormalisation, then the Rayleigh-Ritz check
+        hipLaunchKernelGGL(k_pca_mv, gmv, dim3(256), 0, h->stream, (const double *)Cs, (const double *)V, n, b, T);
+        hipLaunchKernelGGL(k_pca_mv, gmv, dim3(256), 0, h->stream, (const double *)Cs, (const double *)T, n, b, V);
+        hipLaunchKernelGGL(k_pca_orth, dim3(1), dim3(256), 0, h->stream, V, n, b, it);
+        hipLaunchKernelGGL(k_pca_mv, gmv, dim3(256), 0, h->stream, (const double *)Cs, (const double *)V, n, b, T);
+        hipLaunchKernelGGL(k_pca_rr, dim3(1), dim3(256), 0, h->stream, V, T, n, b, k, out);
+        SAP_LAUNCHED(h, "subspace iteration");
+        SAP_HIP(h, hipMemcpyAsync(hout, out, sizeof(double) * (b + 1), hipMemcpyDeviceToHost, h->stream));
+        SAP_HIP(h, hipStreamSynchronize(h->stream));
+        if (hout[b] <= 1e-12) { conv = true; break; }
+    }
+    hipLaunchKernelGGL(k_pca_out, dim3(1), dim3(256), 0, h->stream, (const double *)V, n, b, k, P);
+    SAP_LAUNCHED(h, "k_pca_out");
+    SAP_HIP(h, hipEventRecord(e1, h->stream));
+    if (P_out) SAP_HIP(h, hipMemcpyAsync(P_out, P, sizeof(double) * n * k, hipMemcpyDeviceToDevice, h->stream));
+    SAP_HIP(h, hipStreamSynchronize(h->stream));
+    float ms = 0.0f;
+    SAP_HIP(h, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        for (int c = 0; c < k; ++c) info->sigma[c] = std::sqrt(std::max(hout[c], 0.0));
+        info->residual = hout[b];
+        info->ms = ms;
+        info->iters = std::min(it, 400);
+        info->converged = conv ? 1 : 0;
+    }
+    if (set_P) SAP_TRY(load_P(h, P));
+    return SAP_OK;
+}
+
+// ---------------------------------------------------------------- C ABI// ---------------------------------------------------------------- C ABI
 
 extern "C" {
 
@@ -858,6 +958,12 @@ sap_status sap_set_P(sap_handle h, const double *P) {
     SAP_TRY(usable(h));
     if (!P) return fail(h, SAP_ERR_INVALID_ARG, "null P");
     return load_P(h, P);
+}
+
+sap_status sap_pca_init(sap_handle h, double *P_out, sap_pca_info *info, int32_t set_P) {
+    SAP_TRY(usable(h));
+    if (h->cfg.dtype == SAP_F64) return pca_run<double>(h, P_out, info, set_P != 0);
+    return pca_run<float>(h, P_out, info, set_P != 0);
 }
 
 sap_status sap_set_stream(sap_handle h, void *stream) {

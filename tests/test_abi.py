@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(sap._SIGS)
 
 
-MIRRORED = ("sap_config", "sap_min_result", "sap_info_t", "sap_profile_t", "sap_batch_problem",
+MIRRORED = ("sap_config", "sap_min_result", "sap_info_t", "sap_profile_t", "sap_batch_problem", "sap_pca_info",
             "sap_batch_stats")
 
 

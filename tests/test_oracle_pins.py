@@ -307,6 +307,78 @@ def test_orth_error_flags_non_orthonormal_bases():
     assert oracle.orth_error(P) <= 2.0 ** -52
 
 
+# ---------------------------------------------------------------- initial projection
+
+def test_pca_right_triangle_by_hand():
+    """Algorithm 1's start, pinned by hand: the points (0,0), (1,0), (0,1)
+    give the unit secants (-1,0), (0,-1), (1,-1)/sqrt2, so
+    S S^T = [[3/2, -1/2], [-1/2, 3/2]]: singular values sqrt2 and 1, the
+    first left singular vector (1, -1)/sqrt2."""
+    X = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    S = oracle.secant_matrix(X)
+    assert np.allclose(S @ S.T, [[1.5, -0.5], [-0.5, 1.5]], atol=1e-15)
+    P, sv, _ = oracle.pca_init(X, 2)
+    assert np.allclose(sv, [np.sqrt(2.0), 1.0], atol=1e-15)
+    assert np.allclose(P[:, 0], [1 / np.sqrt(2.0), -1 / np.sqrt(2.0)], atol=1e-15)
+    assert np.allclose(P[:, 1], [1 / np.sqrt(2.0), 1 / np.sqrt(2.0)], atol=1e-15)
+
+
+def test_pca_regular_octagon_is_isotropic():
+    """The vertices of a regular octagon: the 28 secants are invariant under
+    the rotation by 45 degrees, so S S^T is a multiple of I: both singular
+    values are sqrt(28 / 2)."""
+    a = 2 * np.pi * np.arange(8) / 8
+    X = np.stack([np.cos(a), np.sin(a)], axis=1)
+    _, sv, _ = oracle.pca_init(X, 2)
+    assert np.allclose(sv, [np.sqrt(14.0)] * 2, atol=1e-13)
+
+
+def test_pca_planar_data_spans_the_plane():
+    """Points on an affine k-plane: every secant lies in the plane, so the top
+    k left singular vectors span it and the other singular values are 0."""
+    rng = np.random.default_rng(5)
+    A = sap_inputs.random_orthonormal(rng, 9, 3)
+    X = rng.standard_normal((60, 3)) @ A.T + 0.3
+    P, sv, allsv = oracle.pca_init(X, 3)
+    assert np.abs(P @ P.T - A @ A.T).max() < 1e-12
+    assert allsv[3:].max() < 1e-12 * allsv[0]
+
+
+def test_pca_trace_counts_kept_pairs_and_is_rotation_equivariant():
+    """sum sigma^2 = trace S S^T = the number of kept unit secants (with
+    duplicates and a length threshold dropping some), and rotating the data
+    rotates the singular vectors: P(X R^T) spans R span(P(X))."""
+    w = sap_inputs.make("trig10", N=70)
+    X = w.X.copy()
+    X[11] = X[4]
+    X[40] = X[4]
+    ref = oracle.min_secant(X, w.P0, min_len=0.6)
+    _, _, allsv = oracle.pca_init(X, 3, min_len=0.6)
+    assert abs((allsv ** 2).sum() - ref["n_pairs"]) < 1e-9 * ref["n_pairs"]
+    R = sap_inputs.random_orthonormal(np.random.default_rng(8), 10, 10)
+    P, _, sv = oracle.pca_init(X, 4, min_len=0.6)
+    PR, _, svR = oracle.pca_init(X @ R.T, 4, min_len=0.6)
+    assert sv[3] - sv[4] > 1e-3 * sv[0]          # a gap after the fourth value
+    assert np.abs(PR @ PR.T - R @ P @ P.T @ R.T).max() < 1e-10
+    assert np.allclose(sv, svR, rtol=1e-12)
+
+
+def test_secant_matrix_matches_the_laplacian_form():
+    """S S^T by another route: sum_{i<j} w_ij (x_i - x_j)(x_i - x_j)^T with
+    w_ij = 1/d_ij^2 equals X^T L X for the weighted graph Laplacian
+    L = diag(W 1) - W (an identity of the weights, not the oracle's loop)."""
+    w = sap_inputs.make("hyper", N=90, k=3)
+    X = w.X.astype(np.float64)
+    S = oracle.secant_matrix(X)
+    D2 = ((X[:, None, :] - X[None, :, :]) ** 2).sum(-1)
+    Wm = np.zeros_like(D2)
+    off = ~np.eye(len(X), dtype=bool)
+    Wm[off] = 1.0 / D2[off]
+    L = np.diag(Wm.sum(1)) - Wm
+    C = X.T @ L @ X
+    assert np.abs(S @ S.T - C).max() < 1e-9 * np.abs(C).max()
+
+
 # ---------------------------------------------------------------- loop
 
 def test_run_trace_and_orthonormality():
