@@ -1,21 +1,27 @@
 #!/usr/bin/env python3
 """Projected secants/s and ms per SAP iteration, fused vs plain.
 
-Workload: the trigonometric moment curve with harmonics 1..32 (n = 64),
-N = 4,000 points (7,998,000 unit secants), FP32 input, projection to k = 6
-from the seeded random orthonormal start, alpha = 0.01 -- the curve of the
-paper's Sec. 5 at the scale where both forms of the pass fit one GPU.
+Headline workload: the trigonometric moment curve with harmonics 1..32
+(n = 64), N = 4,000 points (7,998,000 unit secants), FP32 input, projection
+to k = 6 from the seeded random orthonormal start, alpha = 0.01 -- the curve
+of the paper's Sec. 5 at the scale where both forms of the pass fit one GPU.
 
 A timed step is one SAP iteration: evaluate every secant, reduce to the
 FP64-rescored min/argmin, apply the update.  `value` is the fused form's
-secants/s (kept pairs x timed iterations / wall time of the timed region,
-inputs resident in HBM); the plain form is reported beside it.
+secants/s (kept pairs x timed iterations / time of the timed region, inputs
+resident in HBM); the plain form is reported beside it.  `roofline` is the
+fused pair pass's: 4 B of 1/d^2 per pair over its average launch duration,
+from the kernel's own dispatch timestamps on the library's stream.
 
-A second leg times the soft-min surrogate on the synthetic hyperspectral
-workload (N = 20,000 pixels, n = 200 bands, k = 10, tau = 0.01): forward +
-hand-written backward through the library, then Adam on P and a sign-fixed
-QR retraction in torch, per step.
-
+Further legs (extra keys, each with secants/s, ms per iteration and the
+roofline fraction of its dominant kernel):
+  trig10    the paper's Sec. 5 curve, N = 200, n = 10, FP64, k = 3, plain, 200 iterations
+  blob      rotated-image stand-in, N = 8,000, n = 1024, k = 2 / 4 / 8, fused, 300 iterations
+  hyper     soft-min fwd + bwd + Adam + QR on the hyperspectral stand-in (N = 20,000, n = 200, k = 10)
+  torus     N = 40,000, n = 256, k = 16: fused iterations and a soft-min fwd + bwd
+  pca       Algorithm 1's secant-PCA start (trig64 and hyper)
+  batch     many small problems per launch: the dimension sweep of Sec. 6.1,
+            subsamples of Sec. 6.3, the length threshold of Sec. 7
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -31,8 +37,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
-VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: lane-instructions/s
+HBM_PEAK_GBS = 8000.0                  # MI355X HBM3E
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: lane-instructions/s (FP32 or FP64)
 
 
 def log(msg):
@@ -63,7 +69,9 @@ def measured_traffic():
     return float(kv["traffic_bytes_per_launch"].split()[0])
 
 
-def time_form(torch, ctx, steps, warmup, prof_steps):
+def time_run(torch, ctx, steps, warmup, prof_steps):
+    """sap_run timed from the seeded start: wall clock and events around
+    the run, then the per-kernel durations of a second, profiled run."""
     dev = torch.device("cuda:0")
     m = steps + 1
     out = dict(min=torch.empty(m, dtype=torch.float64, device=dev),
@@ -72,7 +80,7 @@ def time_form(torch, ctx, steps, warmup, prof_steps):
     P0 = ctx.get_P()
     if warmup:
         ctx.run(warmup)
-    ctx.set_P(P0)                                   # timed run starts at the seeded P0
+    ctx.set_P(P0)                                   # the timed run starts at the seeded P0
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -83,7 +91,6 @@ def time_form(torch, ctx, steps, warmup, prof_steps):
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
     P_final = ctx.get_P().cpu().numpy()
-    # per-kernel durations, HIP events on the library's stream, same work
     ctx.set_P(P0)
     ctx.profile(True)
     ctx.run(prof_steps)
@@ -93,14 +100,70 @@ def time_form(torch, ctx, steps, warmup, prof_steps):
                 P_final=P_final, profile=prof)
 
 
-def softmin_leg(torch, np, steps, warmup):
-    """ms per soft-min optimisation step (fwd + bwd + Adam + QR) and the
-    library's per-kernel split, on the hyperspectral workload."""
-    import sap_inputs
+def sap_leg(torch, np, w, form, steps, warmup, gemm="f64", prof_steps=None, keep=False):
+    """One workload through sap_run: throughput, per-kernel durations and the
+    pair pass's roofline (HBM: 4 B of 1/d^2 per pair fused, n x dtype bytes
+    per stored secant plain)."""
+    from paper_1807_03425_amd import SapContext
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(w.X).to(dev)
+    t = time.perf_counter()
+    ctx = SapContext(X, torch.from_numpy(w.P0), form=form, alpha=w.alpha, gemm=gemm)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t
+    info = ctx.info()
+    r = time_run(torch, ctx, steps, warmup, prof_steps or min(steps, 200))
+    pairs = info["n_pairs"]
+    tsec = max(r["wall_s"], r["event_ms"] / 1e3)
+    prof = r["profile"]
+    kern = {k: v["ms"] * 1e3 / v["launches"] for k, v in prof.items() if v["launches"]}
+    es = w.X.dtype.itemsize
+    pass_us = kern.get("pass")
+    bytes_launch = 4 * pairs if form == "fused" else es * w.n * pairs
+    out = dict(
+        workload=f"{w.name}: N={w.N}, n={w.n}, k={w.k}, {w.X.dtype}, {form}, gemm={gemm}",
+        pairs=pairs, iters=steps, secants_per_s=pairs * steps / tsec, ms_per_iter=tsec * 1e3 / steps,
+        init_s=init_s, certified_frac=float(np.mean(r["trace"]["certified"] == 1)),
+        kernel_us_per_launch=kern, n_close=info["n_close"], e_abs=info["e_abs"],
+        final_min=float(r["trace"]["min"][-1]))
+    if pass_us:
+        gbs = bytes_launch / (pass_us * 1e-6) / 1e9
+        out["roofline"] = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                               frac=gbs / HBM_PEAK_GBS, kernel=f"sap::k_pass<{w.k}, "
+                               f"{'float' if es == 4 else 'double'}, {'true' if form == 'fused' else 'false'}>",
+                               bytes_per_launch=bytes_launch, avg_launch_us=pass_us)
+        if form == "fused":
+            # key arithmetic per pair: K subtractions, K FMAs, a multiply, a min
+            valu = (2 * w.k + 2) * pairs
+            out["roofline_valu"] = dict(bound="alu", lane_instr_per_launch=valu,
+                                        achieved=valu / (pass_us * 1e-6) / 1e12,
+                                        peak=VALU_LANE_OPS / 1e12, unit="T lane-instr/s",
+                                        frac=valu / (pass_us * 1e-6) / VALU_LANE_OPS)
+    if keep:
+        out["_ctx"], out["_run"] = ctx, r
+    else:
+        ctx.close()
+    return out
+
+
+def softmin_slots(K):
+    """Issue slots per pair of the soft-min passes, counting the method's own
+    work (a transcendental -- sqrt, rsq, exp2 -- as 4):
+      forward:  K subtractions + K FMAs (||y_i - y_j||^2), a multiply by
+                1/d^2, a select of masked pairs, sqrt, min, and for the sum
+                an FMA, exp2 and an add: 2K + 14;
+      backward: the same 2K for the norm, multiply, rsq, multiply, FMA,
+                exp2, two multiplies, two compares and a select for the
+                weight, and the contraction's two accumulations (z_j and
+                z_i, K FMAs each): 4K + 16."""
+    return 2 * K + 14, 4 * K + 16
+
+
+def softmin_leg(torch, np, w, tau, steps, warmup, adam=True):
+    """ms per soft-min optimisation step (fwd + bwd (+ Adam + QR)) and the
+    library's per-kernel split."""
     from paper_1807_03425_amd import SapContext, SoftMinSecant
     dev = torch.device("cuda:0")
-    w = sap_inputs.make("hyper")
-    tau = 0.01
     t = time.perf_counter()
     ctx = SapContext(torch.from_numpy(w.X).to(dev), torch.from_numpy(w.P0), form="fused")
     torch.cuda.synchronize()
@@ -113,11 +176,12 @@ def softmin_leg(torch, np, steps, warmup):
         opt.zero_grad(set_to_none=False)
         L = SoftMinSecant.apply(P, ctx, tau)
         L.backward()
-        opt.step()
-        with torch.no_grad():
-            Q, R = torch.linalg.qr(P.detach().double())
-            sg = torch.where(torch.diagonal(R) < 0, -1.0, 1.0).to(Q.dtype)
-            P.copy_((Q * sg.unsqueeze(0)).float())
+        if adam:
+            opt.step()
+            with torch.no_grad():
+                Q, R = torch.linalg.qr(P.detach().double())
+                sg = torch.where(torch.diagonal(R) < 0, -1.0, 1.0).to(Q.dtype)
+                P.copy_((Q * sg.unsqueeze(0)).float())
         return L
 
     losses = []
@@ -142,18 +206,13 @@ def softmin_leg(torch, np, steps, warmup):
     ctx.close()
     pairs = info["n_pairs"]
     kern = {k: v["ms"] / max(v["launches"], 1) for k, v in prof.items() if v["launches"]}
-    # issue slots per pair (transcendentals count 4): forward K sub + K FMA +
-    # mul + select + sqrt + min + FMA + exp2 + add; backward phase 1 K sub +
-    # K FMA + mul + rsq + mul + FMA + exp2 + 2 mul + 2 cmp + select + K FMA,
-    # phase 2 K sub + K FMA
-    K = w.k
-    slots_fwd, slots_bwd = 2 * K + 14, 5 * K + 16
-    out = dict(workload=f"synthetic hyperspectral, N={w.N}, n={w.n}, k={K}, tau={tau}, "
-                        f"Adam lr=1e-3 + sign-fixed QR retraction",
+    sf, sb = softmin_slots(w.k)
+    out = dict(workload=f"{w.name}: N={w.N}, n={w.n}, k={w.k}, tau={tau}"
+                        + (", Adam lr=1e-3 + sign-fixed QR retraction" if adam else ", fwd + bwd"),
                pairs=pairs, steps=steps, warmup=warmup, ms_per_step=ms, init_s=init_s,
                loss_first=float(losses[0]), loss_last=float(losses[-1]),
                kernel_ms_per_launch=kern)
-    for slot, slots in (("sm_fwd", slots_fwd), ("sm_bwd", slots_bwd)):
+    for slot, slots in (("sm_fwd", sf), ("sm_bwd", sb)):
         if slot in kern:
             ach = slots * pairs / (kern[slot] / 1e3)
             out[f"roofline_{slot}"] = dict(bound="alu", achieved=ach / 1e12, peak=VALU_LANE_OPS / 1e12,
@@ -162,16 +221,63 @@ def softmin_leg(torch, np, steps, warmup):
     return out
 
 
+def pca_leg(torch, np, w):
+    from paper_1807_03425_amd import SapContext
+    dev = torch.device("cuda:0")
+    ctx = SapContext(torch.from_numpy(w.X).to(dev), torch.from_numpy(w.P0), form="fused")
+    ctx.pca_init()                      # warm
+    t = time.perf_counter()
+    _, info = ctx.pca_init(set_P=True)
+    wall = time.perf_counter() - t
+    r0 = ctx.min_secant()
+    ctx.close()
+    return dict(workload=f"{w.name}: N={w.N}, n={w.n}, k={w.k}", device_ms=info["ms"], wall_ms=wall * 1e3,
+                iters=info["iters"], residual=info["residual"], converged=info["converged"],
+                sigma=info["sigma"], min_at_pca_start=r0["min_norm"])
+
+
+def batch_leg(torch, np, name, X, sets, problems, P0s, iters, set_min_len=None):
+    """One batch of small problems in one launch: total secants/s of the run
+    kernel, ms per iteration, and the run kernel's VALU fraction (each problem
+    is one workgroup: one compute unit of the 256 at most)."""
+    from paper_1807_03425_amd import batch_run
+    dev = torch.device("cuda:0")
+    Xt = torch.from_numpy(X).to(dev)
+    batch_run(Xt, sets, problems, P0s, 2, set_min_len=set_min_len)     # warm
+    out = batch_run(Xt, sets, problems, P0s, iters, set_min_len=set_min_len)
+    st = out["stats"]
+    run_s = st["run_ms"] / 1e3
+    pairs = st["n_pairs"]
+    # per pair and problem: KP subtractions + KP FMAs (FP64), the FP64
+    # multiply by 1/d^2, the conversion to the FP32 key, a min
+    kp = [2 if k <= 2 else 4 if k <= 4 else 8 if k <= 8 else 12 if k <= 12 else 16
+          for k in (q["k"] for q in problems)]
+    ppp = [len(sets[q["set"]]) * (len(sets[q["set"]]) - 1) // 2 for q in problems]
+    valu = sum(p * (2 * k + 3) for p, k in zip(ppp, kp)) * (iters + 1)
+    cert = out["certified"].cpu().numpy()
+    mins = out["min"].cpu().numpy()
+    return dict(workload=name, problems=len(problems), sets=len(sets), iters=iters,
+                pairs_per_eval=pairs, init_ms=st["init_ms"], run_ms=st["run_ms"],
+                secants_per_s=pairs * (iters + 1) / run_s, ms_per_iter=st["run_ms"] / (iters + 1),
+                certified_frac=float(np.mean(cert == 1)),
+                roofline=dict(bound="alu", achieved=valu / run_s / 1e12, peak=VALU_LANE_OPS / 1e12,
+                              unit="T lane-instr/s", frac=valu / run_s / VALU_LANE_OPS,
+                              note=f"one workgroup per problem: at most {len(problems)} of 256 compute units"),
+                final_min_by_problem=[float(v) for v in mins[:, -1]])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500, help="timed SAP iterations per form")
+    ap.add_argument("--steps", type=int, default=500, help="timed SAP iterations per form (headline)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--forms", default="fused,plain")
+    ap.add_argument("--legs", default="trig10,blob,hyper,torus,pca,batch",
+                    help="further legs (comma list; empty = headline only)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the FP64 CPU oracle baseline (0 disables it)")
     ap.add_argument("--softmin-steps", type=int, default=20,
-                    help="timed soft-min optimisation steps on the hyperspectral workload (0 disables)")
+                    help="timed soft-min optimisation steps on the hyperspectral workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-MiB device buffer 3 times (a kernel of known traffic, "
                          "to scale rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -187,7 +293,6 @@ def main():
     import torch
 
     import sap_inputs
-    from paper_1807_03425_amd import SapContext
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -203,70 +308,22 @@ def main():
         log(f"copy calibration: 3 copies of {nb} bytes")
         del src, dst
     w = sap_inputs.make("trig64")
-    X = torch.from_numpy(w.X).to(dev)
-    P0 = torch.from_numpy(w.P0)
     forms = [f for f in args.forms.split(",") if f]
     res = {}
     for form in forms:
-        t = time.perf_counter()
-        ctx = SapContext(X, P0, form=form, alpha=w.alpha)
-        torch.cuda.synchronize()
-        init_s = time.perf_counter() - t
-        info = ctx.info()
-        log(f"{form}: init {init_s:.3f}s, pairs {info['n_pairs']}, close {info['n_close']}, "
-            f"e_abs {info['e_abs']:.3g}")
-        r = time_form(torch, ctx, args.steps, args.warmup, min(args.steps, 200))
-        r.update(info=info, init_s=init_s)
-        ms = r["event_ms"] / args.steps
-        log(f"{form}: {args.steps} iterations in {r['event_ms']:.2f} ms (events), "
-            f"{r['wall_s']*1e3:.2f} ms (wall) -> {ms*1e3:.1f} us/iter")
+        r = sap_leg(torch, np, w, form, args.steps, args.warmup, keep=True)
+        log(f"{form}: {args.steps} iterations, {r['ms_per_iter'] * 1e3:.1f} us/iter, "
+            f"pass {r['kernel_us_per_launch'].get('pass', 0):.2f} us")
         res[form] = r
-        ctx.close()
-        del ctx
-        torch.cuda.synchronize()
-
-    def summary(form):
-        r = res[form]
-        info = r["info"]
-        t = max(r["wall_s"], r["event_ms"] / 1e3)
-        pairs = info["n_pairs"]
-        prof = r["profile"]
-        p = prof["pass"]
-        avg_pass_s = p["ms"] / max(p["launches"], 1) / 1e3
-        per_iter_ms = {k: v["ms"] / max(v["launches"], 1) for k, v in prof.items() if v["launches"]}
-        if form == "fused":
-            bytes_launch = 4 * pairs                       # one FP32 1/d^2 per pair
-            valu = (2 * w.k + 2) * pairs                   # lane-instructions per launch
-        else:
-            bytes_launch = 4 * w.n * pairs                 # n FP32 components per stored secant
-            valu = (w.n * w.k + w.k) * pairs
-        return dict(
-            secants_per_s=pairs * args.steps / t,
-            ms_per_iter=t * 1e3 / args.steps,
-            init_s=r["init_s"],
-            certified_frac=float(np.mean(r["trace"]["certified"] == 1)),
-            kernel_ms_per_launch=per_iter_ms,
-            pass_kernel=dict(avg_us=avg_pass_s * 1e6, bytes_per_launch=bytes_launch,
-                             gbs=bytes_launch / avg_pass_s / 1e9 if avg_pass_s > 0 else None,
-                             valu_lane_instr_per_launch=valu,
-                             valu_frac=valu / avg_pass_s / VALU_LANE_OPS if avg_pass_s > 0 else None),
-            n_close=info["n_close"], e_abs=info["e_abs"],
-        )
-
-    sums = {f: summary(f) for f in res}
-    head = "fused" if "fused" in sums else forms[0]
-    hs = sums[head]
-    pk = hs["pass_kernel"]
+    head = "fused" if "fused" in res else forms[0]
+    hs = res[head]
     traffic = measured_traffic() if head == "fused" else None
-    roofline = dict(bound="hbm", achieved=pk["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=(pk["gbs"] / HBM_PEAK_GBS) if pk["gbs"] else None, traffic=traffic,
-                    kernel=f"sap::k_pass<{w.k}, float, {'true' if head == 'fused' else 'false'}>",
-                    bytes_per_launch=pk["bytes_per_launch"],
-                    avg_launch_us=pk["avg_us"], valu_frac=pk["valu_frac"])
+    roofline = dict(hs["roofline"], traffic=traffic,
+                    valu_frac=hs.get("roofline_valu", {}).get("frac"))
 
     accuracy = {}
     if "fused" in res and "plain" in res:
-        a, b = res["fused"]["trace"], res["plain"]["trace"]
+        a, b = res["fused"]["_run"]["trace"], res["plain"]["_run"]["trace"]
         same = a["ij"] == b["ij"]
         first_diff = int(np.argmin(same.all(axis=1))) if not same.all() else None
         upto = first_diff if first_diff is not None else len(a["min"])
@@ -298,13 +355,18 @@ def main():
         log(f"cpu baseline: {it} iterations in {dt:.1f}s")
         # accuracy of the timed GPU runs: the oracle scores each form's final P
         for form, r in res.items():
-            ref = oracle.min_secant(w.X, r["P_final"])
-            gmin, gij = r["trace"]["min"][-1], tuple(r["trace"]["ij"][-1])
+            tr = r["_run"]["trace"]
+            ref = oracle.min_secant(w.X, r["_run"]["P_final"])
+            gmin, gij = tr["min"][-1], tuple(tr["ij"][-1])
             accuracy[form] = dict(
                 final_min_gpu=float(gmin), final_min_oracle=ref["r_min"],
                 rel_err=abs(gmin - ref["r_min"]) / ref["r_min"],
                 argmin_match=gij == (ref["i"], ref["j"]),
                 oracle_gap_to_runner_up=ref["r_second"] - ref["r_min"])
+    for r in res.values():
+        r["_ctx"].close()
+        del r["_ctx"], r["_run"]
+    torch.cuda.synchronize()
 
     line = dict(
         metric="projected secants/sec + ms per SAP iteration, fused vs plain at stated accuracy",
@@ -314,23 +376,72 @@ def main():
         data="synthetic",
         config=dict(workload="trig moment curve, harmonics 1..32 (n=64), N=4000, FP32, k=6, "
                              "alpha=0.01, seeded random orthonormal start",
-                    form=head, pairs=res[head]["info"]["n_pairs"],
+                    form=head, pairs=hs["pairs"],
                     arithmetic="FP32 coarse pass; FP64 GEMM (fused), FP64 rescoring and update"),
-        roofline=roofline, cpu_baseline=cpu, forms=sums, accuracy=accuracy,
+        roofline=roofline, cpu_baseline=cpu, forms=res, accuracy=accuracy,
     )
-    if "plain" in sums:
-        pp = sums["plain"]["pass_kernel"]
-        line["roofline_plain"] = dict(bound="hbm", achieved=pp["gbs"], peak=HBM_PEAK_GBS,
-                                      unit="GB/s", frac=pp["gbs"] / HBM_PEAK_GBS if pp["gbs"] else None,
-                                      traffic=None, kernel=f"sap::k_pass<{w.k}, float, false>",
-                                      bytes_per_launch=pp["bytes_per_launch"],
-                                      avg_launch_us=pp["avg_us"])
-        if "fused" in sums:
-            line["fused_over_plain"] = sums["fused"]["secants_per_s"] / sums["plain"]["secants_per_s"]
-    if args.softmin_steps > 0:
-        log("soft-min leg: hyperspectral workload")
-        line["softmin"] = softmin_leg(torch, np, args.softmin_steps, 3)
+    if "plain" in res:
+        line["roofline_plain"] = dict(res["plain"]["roofline"], traffic=None)
+        if "fused" in res:
+            line["fused_over_plain"] = res["fused"]["secants_per_s"] / res["plain"]["secants_per_s"]
+
+    legs = [l for l in args.legs.split(",") if l]
+    if "trig10" in legs:
+        log("leg trig10 (paper Sec. 5 curve, plain FP64, 200 iterations)")
+        line["trig10"] = sap_leg(torch, np, sap_inputs.make("trig10"), "plain", 200, 5)
+    if "blob" in legs:
+        line["blob"] = {}
+        for k in (2, 4, 8):
+            log(f"leg blob k={k} (fused, 300 iterations)")
+            line["blob"][f"k{k}"] = sap_leg(torch, np, sap_inputs.make("blob", k=k), "fused", 300, 5)
+    if "hyper" in legs and args.softmin_steps > 0:
+        log("leg hyper: soft-min optimisation steps")
+        line["softmin"] = softmin_leg(torch, np, sap_inputs.make("hyper"), 0.01, args.softmin_steps, 3)
         log(f"soft-min: {line['softmin']['ms_per_step']:.3f} ms/step")
+    if "torus" in legs:
+        wt = sap_inputs.make("torus")
+        log("leg torus: fused iterations")
+        line["torus"] = dict(iterations=sap_leg(torch, np, wt, "fused", 100, 3, prof_steps=20))
+        log("leg torus: soft-min fwd + bwd")
+        line["torus"]["softmin"] = softmin_leg(torch, np, wt, 0.01, 3, 1, adam=False)
+    if "pca" in legs:
+        line["pca_init"] = {}
+        for nm in ("trig64", "hyper"):
+            log(f"leg pca: {nm}")
+            line["pca_init"][nm] = pca_leg(torch, np, sap_inputs.make(nm))
+    if "batch" in legs:
+        line["batch"] = {}
+        ks = list(range(1, 11))
+        log("leg batch: dimension sweep (Sec. 6.1)")
+        X = np.concatenate([sap_inputs.embedded_manifold(kd, 256, 10 + e)
+                            for e, kd in enumerate(("curve", "torus", "sphere"))])
+        sets = [np.arange(e * 256, (e + 1) * 256, dtype=np.int32) for e in range(3)]
+        probs = [dict(set=s, k=k) for s in range(3) for k in ks]
+        line["batch"]["sweep"] = batch_leg(
+            torch, np, "curve / 2-torus / 3-sphere in R^15, 256 points each, k = 1..10, 100 iterations",
+            X, sets, probs, sap_inputs.sweep_starts(15, [q["k"] for q in probs], 21), 100)
+        log("leg batch: subsample ensemble (Sec. 6.3)")
+        wh = sap_inputs.make("hyper")
+        sets = sap_inputs.subsample_sets(wh.N, 10, 512, seed=63)
+        probs = [dict(set=s, k=k) for s in range(10) for k in ks]
+        line["batch"]["subsamples"] = batch_leg(
+            torch, np, "hyperspectral stand-in (N=20000, n=200, FP32): 10 x 512-point subsamples, "
+                       "k = 1..10, 100 iterations",
+            wh.X, sets, probs, sap_inputs.sweep_starts(wh.n, [q["k"] for q in probs], 64), 100)
+        log("leg batch: length threshold (Sec. 7)")
+        Xn, _ = sap_inputs.trig_curve(512, 5, seed=71, noise=0.1)
+        Xc, _ = sap_inputs.trig_curve(512, 5, seed=71)
+        X = np.concatenate([Xc, Xn])
+        sets = [np.arange(512, dtype=np.int32), np.arange(512, 1024, dtype=np.int32),
+                np.arange(512, 1024, dtype=np.int32)]
+        # k = 1..9: at k = n = 10 the projection is the identity and every
+        # pair ties at r = 1
+        probs = [dict(set=s, k=k) for s in range(3) for k in range(1, 10)]
+        line["batch"]["threshold"] = batch_leg(
+            torch, np, "trig curve R^10, 512 points: clean, noisy (sigma 0.1), noisy with l = 2; "
+                       "k = 1..9, 100 iterations",
+            X, sets, probs, sap_inputs.sweep_starts(10, [q["k"] for q in probs], 72), 100,
+            set_min_len=[0.0, 0.0, 2.0])
     print(json.dumps(line), flush=True)
 
 
