@@ -16,9 +16,11 @@ from the kernel's own dispatch timestamps on the library's stream.
 Further legs (extra keys, each with secants/s, ms per iteration and the
 roofline fraction of its dominant kernel):
   trig10    the paper's Sec. 5 curve, N = 200, n = 10, FP64, k = 3, plain, 200 iterations
-  blob      rotated-image stand-in, N = 8,000, n = 1024, k = 2 / 4 / 8, fused, 300 iterations
+  blob      rotated-image stand-in, N = 8,000, n = 1024, k = 2 / 4 / 8, fused, 300 iterations,
+            BF16 Y GEMM (the configuration's) and FP64 Y GEMM
   hyper     soft-min fwd + bwd + Adam + QR on the hyperspectral stand-in (N = 20,000, n = 200, k = 10)
-  torus     N = 40,000, n = 256, k = 16: fused iterations and a soft-min fwd + bwd
+  torus     N = 40,000, n = 256, k = 16: fused iterations (BF16 and FP64 Y GEMM) and a
+            soft-min fwd + bwd
   pca       Algorithm 1's secant-PCA start (trig64 and hyper)
   batch     many small problems per launch: the dimension sweep of Sec. 6.1,
             subsamples of Sec. 6.3, the length threshold of Sec. 7
@@ -392,16 +394,20 @@ def main():
     if "blob" in legs:
         line["blob"] = {}
         for k in (2, 4, 8):
-            log(f"leg blob k={k} (fused, 300 iterations)")
-            line["blob"][f"k{k}"] = sap_leg(torch, np, sap_inputs.make("blob", k=k), "fused", 300, 5)
+            for g in ("bf16", "f64"):
+                log(f"leg blob k={k} (fused, {g} Y GEMM, 300 iterations)")
+                line["blob"][f"k{k}_{g}"] = sap_leg(torch, np, sap_inputs.make("blob", k=k), "fused", 300, 5,
+                                                    gemm=g)
     if "hyper" in legs and args.softmin_steps > 0:
         log("leg hyper: soft-min optimisation steps")
         line["softmin"] = softmin_leg(torch, np, sap_inputs.make("hyper"), 0.01, args.softmin_steps, 3)
         log(f"soft-min: {line['softmin']['ms_per_step']:.3f} ms/step")
     if "torus" in legs:
         wt = sap_inputs.make("torus")
-        log("leg torus: fused iterations")
-        line["torus"] = dict(iterations=sap_leg(torch, np, wt, "fused", 100, 3, prof_steps=20))
+        line["torus"] = {}
+        for g in ("bf16", "f64"):
+            log(f"leg torus: fused iterations, {g} Y GEMM")
+            line["torus"][f"iterations_{g}"] = sap_leg(torch, np, wt, "fused", 100, 3, gemm=g, prof_steps=20)
         log("leg torus: soft-min fwd + bwd")
         line["torus"]["softmin"] = softmin_leg(torch, np, wt, 0.01, 3, 1, adam=False)
     if "pca" in legs:

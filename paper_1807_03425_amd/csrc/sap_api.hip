@@ -205,8 +205,6 @@ static sap_status validate(const sap_config *c, int64_t ldx, const void *X, cons
         return fail(nullptr, SAP_ERR_INVALID_ARG, "cand_cap must lie in [0, %d] (0 = %d)", kCandCap, kCandCap);
     if (c->gemm != SAP_GEMM_F64 && c->gemm != SAP_GEMM_F32 && c->gemm != SAP_GEMM_BF16)
         return fail(nullptr, SAP_ERR_INVALID_ARG, "gemm must be SAP_GEMM_F64, SAP_GEMM_F32 or SAP_GEMM_BF16");
-    if (c->gemm != SAP_GEMM_F64)
-        return fail(nullptr, SAP_ERR_UNSUPPORTED, "only SAP_GEMM_F64 is built");
     if (c->gemm != SAP_GEMM_F64 && c->form != SAP_FUSED)
         return fail(nullptr, SAP_ERR_INVALID_ARG, "gemm selects the fused form's Y GEMM: plain form needs SAP_GEMM_F64");
     if (ldx < c->n) return fail(nullptr, SAP_ERR_INVALID_ARG, "ldx must be >= n");
@@ -327,12 +325,27 @@ static sap_status init_fused(sap_ctx *h) {
     SAP_HIP(h, hipMemcpyAsync(h->d_tiles, tiles.data(), sizeof(int2) * h->ntiles,
                               hipMemcpyHostToDevice, h->stream));
 
-    // Coarse error: ||y~_i - y_i|| <= u32 ||y_i|| + FP64 terms <= R (u32 + ...),
-    // so |r~ - r| <= 2 R (u32 + ...) / d.  The automatic cutoff aims at an
-    // absolute error of SAP_EABS_TARGET for every pair left to the coarse pass.
-    const double delta = h->radius * (kU32 * 1.001 + (h->n + 2) * std::sqrt((double)h->k) * kU64 * 4.0);
+    // Coarse error: ||y~_i - y_i|| <= delta, so |r~ - r| <= 2 delta / d.
+    //   FP64 GEMM: delta = R (u32 + (n + 2) sqrt(k) 4 u64) (rounding Y to FP32);
+    //   FP32 GEMM: operands rounded (u32 each) and FP32 accumulation over n
+    //     terms: per component (n + 3) u32 sum_l |x_l - mu_l| |P_lc| <=
+    //     (n + 3) u32 R, so delta = sqrt(k) (n + 3) u32 R;
+    //   BF16 GEMM: operands rounded to BF16 (2^-8 each, through FP32), exact
+    //     products, FP32 accumulation: delta = sqrt(k) (2^-7 + 2^-15 +
+    //     (n + 1) u32) R.
+    // The automatic cutoff aims at an absolute error of SAP_EABS_TARGET for
+    // every pair left to the coarse pass.
+    const double sk = std::sqrt((double)h->k);
+    double delta = h->radius * (kU32 * 1.001 + (h->n + 2) * sk * kU64 * 4.0);
+    if (h->cfg.gemm == SAP_GEMM_F32) delta = h->radius * sk * (h->n + 3) * kU32 * 1.01;
+    if (h->cfg.gemm == SAP_GEMM_BF16)
+        delta = h->radius * sk * (std::ldexp(1.0, -7) + std::ldexp(1.0, -15) + (h->n + 1) * kU32) * 1.01;
     const bool automatic = h->cfg.close_d < 0.0;
-    double dtarget = automatic ? 2.0 * delta / SAP_EABS_TARGET : h->cfg.close_d;
+    // no pair is longer than 2R: an automatic ladder starts there at most
+    // (a wide bound -- a BF16 GEMM -- would otherwise start it far above
+    // every distance and let its 64 rungs end above the shortest pairs)
+    double dtarget = automatic ? std::min(2.0 * delta / SAP_EABS_TARGET, 2.0 * h->radius * (1.0 + 1e-9))
+                               : h->cfg.close_d;
     std::vector<float> ladder(64);
     for (int m = 0; m < 64; ++m) {
         const double D = dtarget * std::pow(2.0, -m / 4.0);
@@ -533,6 +546,7 @@ static SweepArgs<TX> sweep_args(sap_ctx *h, double *tr_min, int64_t *tr_ij, int3
     a.tr_cert = tr_cert;
     a.it = it;
     a.cap = h->cfg.cand_cap > 0 ? h->cfg.cand_cap : kCandCap;
+    a.gemm = h->cfg.gemm;
     return a;
 }
 
@@ -709,6 +723,7 @@ static SmArgs sm_args(sap_ctx *h, double tau) {
     a.P64t = h->d_smP64t;
     a.vx = h->vec_x;
     a.vp = h->vec_p;
+    a.gemm = h->cfg.gemm;
     a.tau = tau;
     a.c2 = (float)(1.4426950408889634 / tau);   // log2(e) / tau
     a.part = h->d_smpart;

@@ -141,16 +141,115 @@ __device__ __forceinline__ void gemm_first_x(const TX *__restrict__ X, int64_t l
     load16(mu + 16 * (lane >> 4), true, ma);
 }
 
-// x0, m0 (optional): the first chunk's X values and means, loaded earlier
-// by gemm_first_x.
+typedef float float4_mfma __attribute__((ext_vector_type(4)));
+typedef short bf16x4_bits __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float f) { return __builtin_bit_cast(short, static_cast<__bf16>(f)); }
+
+// The same 16 x 16 tile of Y with FP32 or BF16 operands and FP32
+// accumulation (gemm = SAP_GEMM_F32: v_mfma_f32_16x16x4f32, one component
+// per lane and k-slot, components mapped as in the FP64 routine; SAP_GEMM_BF16:
+// v_mfma_f32_16x16x16bf16_1k, lane (m, kk) feeding its 16 consecutive
+// components of a 64-component chunk as k-slots 4 kk .. 4 kk + 3 of four
+// MFMAs).  x - mu is formed in FP64 and rounded once to FP32 (then to BF16);
+// P is rounded the same way.  Output layout of both instructions (measured on
+// gfx950 with an in-bounds probe): lane holds rows 4 (lane / 16) + v,
+// v = 0..3, column lane % 16.
 template <typename TX>
-__device__ void gemm_block(const TX *__restrict__ X, int64_t ldx, int64_t N, int n, int k,
+__device__ __forceinline__ void gemm_block_lowp(const TX *__restrict__ X, int64_t ldx, int64_t N, int n, int k,
+                                                const double *__restrict__ mu, const double *__restrict__ P64t,
+                                                float *__restrict__ Y, int kp, int64_t row0, bool vx, bool vp,
+                                                const double (&x0)[16], const double (&m0)[16], bool use_x0,
+                                                int gemm) {
+    const int lane = threadIdx.x & 63;
+    const int m = lane & 15, kk = lane >> 4;
+    const int64_t row = row0 + m;
+    const bool rin = row < N;
+    const double rmask = rin ? 1.0 : 0.0, pmask = m < k ? 1.0 : 0.0;
+    const TX *xr = X + (rin ? row : N - 1) * ldx;
+    const double *pc = P64t + (int64_t)(m < k ? m : k - 1) * n;
+    float4_mfma acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    int l0 = 0;
+    for (; l0 + 64 <= n; l0 += 64) {
+        double xa[16], ma[16], pb[16];
+        const int lb = l0 + 16 * kk;
+        if (use_x0 && l0 == 0) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) { xa[u] = x0[u]; ma[u] = m0[u]; }
+        } else {
+            load16(xr + lb, vx, xa);
+            load16(mu + lb, true, ma);
+        }
+        load16(pc + lb, vp, pb);
+        if (gemm == SAP_GEMM_F32) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32((float)((xa[s] - ma[s]) * rmask), (float)(pb[s] * pmask),
+                                                           acc, 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                bf16x4_bits a4, b4;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a4[u] = bf16_bits((float)((xa[4 * s + u] - ma[4 * s + u]) * rmask));
+                    b4[u] = bf16_bits((float)(pb[4 * s + u] * pmask));
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a4, b4, acc, 0, 0, 0);
+            }
+        }
+    }
+    if (gemm == SAP_GEMM_F32) {
+        for (; l0 < n; l0 += 4) {
+            const int l = l0 + kk;
+            double a = 0.0, b = 0.0;
+            if (l < n) {
+                if (rin) a = (double)xr[l] - mu[l];
+                if (m < k) b = pc[l];
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, acc, 0, 0, 0);
+        }
+    } else {
+        for (; l0 < n; l0 += 16) {
+            bf16x4_bits a4, b4;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int l = l0 + 4 * kk + u;
+                double a = 0.0, b = 0.0;
+                if (l < n) {
+                    if (rin) a = (double)xr[l] - mu[l];
+                    if (m < k) b = pc[l];
+                }
+                a4[u] = bf16_bits((float)a);
+                b4[u] = bf16_bits((float)b);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a4, b4, acc, 0, 0, 0);
+        }
+    }
+    if (m < kp) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t r = row0 + 4 * kk + v;
+            Y[r * kp + m] = (r < N && m < k) ? acc[v] : 0.0f;
+        }
+    }
+}
+
+// x0, m0 (used when use_x0): the first chunk's X values and means, loaded
+// earlier by gemm_first_x.  gemm: SAP_GEMM_F64 (below), or SAP_GEMM_F32 /
+// SAP_GEMM_BF16 (gemm_block_lowp).
+template <typename TX>
+__device__ __forceinline__ void gemm_block(const TX *__restrict__ X, int64_t ldx, int64_t N, int n, int k,
                            const double *__restrict__ mu, const double *__restrict__ P64t,
                            float *__restrict__ Y, int kp, int64_t Npad, bool vx, bool vp,
-                           const double *x0 = nullptr, const double *m0 = nullptr) {
+                           const double (&x0)[16], const double (&m0)[16], bool use_x0, int gemm) {
     const int lane = threadIdx.x & 63;
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
     if (row0 >= Npad) return;
+    if (gemm != SAP_GEMM_F64) {
+        gemm_block_lowp<TX>(X, ldx, N, n, k, mu, P64t, Y, kp, row0, vx, vp, x0, m0, use_x0, gemm);
+        return;
+    }
     const int m = lane & 15, kk = lane >> 4;
     const int64_t row = row0 + m;
     const bool rin = row < N;
@@ -165,7 +264,7 @@ __device__ void gemm_block(const TX *__restrict__ X, int64_t ldx, int64_t N, int
     for (; l0 + 64 <= n; l0 += 64) {
         double xa[16], ma[16], pb[16];
         const int lb = l0 + 16 * kk;
-        if (x0 && l0 == 0) {
+        if (use_x0 && l0 == 0) {
 #pragma unroll
             for (int u = 0; u < 16; ++u) { xa[u] = x0[u]; ma[u] = m0[u]; }
         } else {
@@ -522,6 +621,7 @@ struct SweepArgs {
     int32_t *tr_cert;
     int it;
     int cap;              // candidate-list capacity per wavefront, 1..kCandCap
+    int gemm;             // arithmetic of the Y GEMM: SAP_GEMM_F64 | _F32 | _BF16
 };
 
 // Candidates of a pass block.  The block keeps its running minimum key in
@@ -1063,7 +1163,8 @@ __global__ __launch_bounds__(kPairBlock, (FUSED || sizeof(TX) == 4 || K <= 12) ?
 template <int K, typename TX>
 __global__ __launch_bounds__(kPairBlock) void k_prep(SweepArgs<TX> a, const double *__restrict__ mu,
                                                      float *__restrict__ Y, int64_t Npad) {
-    gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, a.P64t, Y, a.kp, Npad, a.vx, a.vp);
+    const double none[16] = {};
+    gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, a.P64t, Y, a.kp, Npad, a.vx, a.vp, none, none, false, a.gemm);
 }
 
 // ------------------------------------------------------------------ the update
@@ -1497,8 +1598,8 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
         for (int e = threadIdx.x; e < K * a.n; e += kPairBlock) Pn[e] = sm_sp[e];   // P unchanged
     }
     __syncthreads();
-    gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, sm_sp, Y, a.kp, Npad, a.vx, (a.n & 1) == 0,
-                   a.n >= 64 ? x0 : nullptr, m0);
+    gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, sm_sp, Y, a.kp, Npad, a.vx, (a.n & 1) == 0, x0, m0, a.n >= 64,
+                   a.gemm);
 }
 
 #ifndef SAP_KINST   // K-independent kernels: compiled once, in the host runtime unit

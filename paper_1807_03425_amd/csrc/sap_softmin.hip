@@ -51,6 +51,7 @@ struct SmArgs {
     // parameters
     const double *P64t;    // soft-min P, k x n FP64
     int vx, vp;            // 16-byte loads: X rows aligned; n even
+    int gemm;              // arithmetic of the Y GEMM (SAP_GEMM_*)
     double tau;
     float c2;              // log2(e) / tau
     SmPart *part;          // npass + nshort partials (forward)
@@ -147,7 +148,10 @@ __global__ __launch_bounds__(kPairBlock) void k_sm_prep(SmArgs a, const TX *__re
                                                         float *__restrict__ Y, int64_t Npad,
                                                         int gemm_blocks, int bwd) {
     if ((int)blockIdx.x < gemm_blocks)
-        gemm_block<TX>(X, ldx, N, a.n, K, mu, a.P64t, Y, a.kp, Npad, a.vx, a.vp);
+    {
+        const double none[16] = {};
+        gemm_block<TX>(X, ldx, N, a.n, K, mu, a.P64t, Y, a.kp, Npad, a.vx, a.vp, none, none, false, a.gemm);
+    }
     else
         sm_short_block<K, TX>(a, X, ldx, (int)blockIdx.x - gemm_blocks, (int)gridDim.x - gemm_blocks,
                               bwd);

@@ -13,10 +13,12 @@ device's certified result:
 
 Workloads (seeded, synthetic; sap_inputs):
   trig64  N=4000, n=64, k=6, FP32     -- all 500 iterations, fused and plain
-  blob    N=8000, n=1024, k=2/4/8     -- iterations 0, 1, 2
+  blob    N=8000, n=1024, k=2/4/8     -- iterations 0, 1, 2; the first step with
+                                         the BF16 Y GEMM the configuration names
   hyper   N=20000, n=200, k=10        -- iterations 0, 1, 2; soft-min fwd+bwd
-  torus   N=40000, n=256, k=16        -- iteration 0; soft-min at full size
-                                         (properties) and at N=4000 (oracle)
+  torus   N=40000, n=256, k=16        -- iteration 0 (FP64 and BF16 Y GEMM);
+                                         soft-min at full size (properties) and
+                                         at N=4000 (oracle)
 The oracle runs on the host's cores (OpenMP) and takes several minutes in all.
 """
 import time
@@ -46,6 +48,20 @@ def min_tol(r, n, k):
 
 def _say(msg):
     print(f"[fullsize] {msg}", flush=True)
+
+
+_ORACLE = {}
+
+
+def _oracle_min(name, X, P):
+    """oracle.min_secant, remembered per workload and P bytes (the FP64 and
+    BF16 checks of one workload both evaluate its seeded start)."""
+    key = (name, P.tobytes())
+    if key not in _ORACLE:
+        t = time.time()
+        _ORACLE[key] = oracle.min_secant(X, P)
+        _say(f"{name}: oracle {time.time() - t:.1f}s over {_ORACLE[key]['n_pairs']} pairs")
+    return _ORACLE[key]
 
 
 def _compare(Xnp, P, res, ref, tag):
@@ -111,12 +127,42 @@ def test_blob_iterations_0_1_2(k):
     for it in range(3):
         P = ctx.get_P().cpu().numpy()
         res = ctx.step(sync=True)
-        t = time.time()
-        ref = oracle.min_secant(w.X, P)
-        _say(f"blob k={k} it {it}: oracle {time.time() - t:.1f}s, n_rescored {res['n_rescored']}")
+        ref = _oracle_min(f"blob{k}", w.X, P)
+        _say(f"blob k={k} it {it}: n_rescored {res['n_rescored']}")
         _compare(w.X, P, res, ref, f"blob{k}/it{it}")
         _check_step(w.X, P, res, ctx.get_P().cpu().numpy(), w.alpha, f"blob{k}/it{it}")
     ctx.close()
+
+
+def _bf16_first_step(name, k):
+    """The configuration's own arithmetic -- BF16 Y GEMM, FP32 coarse pass,
+    FP64 rescoring: the first evaluation against the oracle.  Certified: the
+    oracle's pair and value; otherwise (overflowing candidate lists) a real
+    pair's exact value within 1e-3 of the oracle's minimum.  The update is
+    checked either way."""
+    w = sap_inputs.make(name, k=k)
+    ctx = SapContext(torch.from_numpy(w.X).to(DEV), torch.from_numpy(w.P0), form="fused", alpha=w.alpha,
+                     gemm="bf16")
+    info = ctx.info()
+    P = ctx.get_P().cpu().numpy()
+    res = ctx.step(sync=True)
+    ref = _oracle_min(f"{name}{k}", w.X, P)
+    r_pair, _ = oracle.pair_r(w.X, P, res["i"], res["j"])
+    assert abs(r_pair - res["min_norm"]) <= min_tol(r_pair, w.n, k)
+    if res["certified"]:
+        _compare(w.X, P, res, ref, f"{name}{k}/bf16")
+    else:
+        assert -1e-12 <= (res["min_norm"] - ref["r_min"]) / ref["r_min"] <= 1e-3, (res, ref)
+    _check_step(w.X, P, res, ctx.get_P().cpu().numpy(), w.alpha, f"{name}{k}/bf16")
+    _say(f"{name} k={k} bf16: certified {res['certified']}, rel err "
+         f"{(res['min_norm'] - ref['r_min']) / ref['r_min']:.1e}, rescored {res['n_rescored']}, "
+         f"short pairs {info['n_close']}, e_abs {info['e_abs']:.2e}")
+    ctx.close()
+
+
+@pytest.mark.parametrize("k", [2, 4, 8])
+def test_blob_bf16_gemm_first_step(k):
+    _bf16_first_step("blob", k)
 
 
 def test_hyper_iterations_0_1_2():
@@ -138,12 +184,14 @@ def test_torus_iteration_0():
     ctx = SapContext(torch.from_numpy(w.X).to(DEV), torch.from_numpy(w.P0), form="fused", alpha=w.alpha)
     P = ctx.get_P().cpu().numpy()
     res = ctx.step(sync=True)
-    t = time.time()
-    ref = oracle.min_secant(w.X, P)
-    _say(f"torus it 0: oracle {time.time() - t:.1f}s over {ref['n_pairs']} pairs")
+    ref = _oracle_min("torus16", w.X, P)
     _compare(w.X, P, res, ref, "torus/it0")
     _check_step(w.X, P, res, ctx.get_P().cpu().numpy(), w.alpha, "torus/it0")
     ctx.close()
+
+
+def test_torus_bf16_gemm_first_step():
+    _bf16_first_step("torus", 16)
 
 
 # ------------------------------------------------------------------ soft-min
