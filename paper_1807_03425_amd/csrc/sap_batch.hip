@@ -274,15 +274,22 @@ __device__ __forceinline__ void batch_gemm16(const TX *__restrict__ X, int64_t l
     }
 }
 
-// The FP64 update of Algorithm 1 for the exact k (K_LO <= k <= K_HI): the
-// block-wide routine of the single-problem handle, P (k x n) staged in LDS,
-// written back to P (global, rows 0..k-1).
+// The FP64 update of Algorithm 1 for the exact k (K_LO <= k <= K_HI), with
+// P (k x n) staged in LDS and written back to P (global, rows 0..k-1): the
+// single-problem handle's routines -- one wavefront with the vectors in
+// registers when n <= 64 and k <= 8, the whole block over LDS otherwise.
+// Every thread of the block calls it.
 template <typename TX, int K_LO, int K_HI>
 __device__ __forceinline__ void batch_update(const TX *X, int64_t ldx, int n, int k, double *P, double alpha, int rule,
                                              int64_t gi, int64_t gj, double *sm) {
     if constexpr (K_LO <= K_HI) {
         if (k == K_LO) {
-            apply_update<K_LO, TX>(X, ldx, n, P, nullptr, 0, alpha, rule, nullptr, gi, gj, sm);
+            if (K_LO <= 8 && n <= kWave) {
+                if (threadIdx.x < kWave)
+                    apply_update_reg<K_LO, 1, TX>(X, ldx, n, sm, P, nullptr, 0, alpha, rule, nullptr, gi, gj, false);
+            } else {
+                apply_update<K_LO, TX>(X, ldx, n, P, nullptr, 0, alpha, rule, nullptr, gi, gj, sm);
+            }
         } else {
             batch_update<TX, K_LO + 1, K_HI>(X, ldx, n, k, P, alpha, rule, gi, gj, sm);
         }
@@ -307,6 +314,19 @@ struct BatchLds {
     Partial fin;
 };
 
+// Tile (bi, bj), bi <= bj, of index t in the row-major order of a set's
+// nb x nb upper triangle (t = bi nb - bi (bi - 1) / 2 + bj - bi): bi from the
+// quadratic, corrected by at most a step each way.  Wavefront-uniform.
+__device__ __forceinline__ int2 tile_of_index(int64_t t, int nb) {
+    auto start = [nb](int64_t b) { return b * nb - b * (b - 1) / 2; };
+    const double q = 2.0 * nb + 1.0;
+    int64_t bi = (int64_t)floor((q - sqrt(fmax(q * q - 8.0 * (double)t, 0.0))) * 0.5);
+    bi = bi < 0 ? 0 : (bi > nb - 1 ? nb - 1 : bi);
+    while (bi > 0 && start(bi) > t) --bi;
+    while (bi + 1 < nb && start(bi + 1) <= t) ++bi;
+    return make_int2((int)bi, (int)(bi + (t - start(bi))));
+}
+
 // One problem, the whole run.  Every thread of the block calls it.
 template <int KP, typename TX>
 __device__ void batch_problem(const BatchArgs &a, int b, double *sm, BatchLds &L) {
@@ -327,7 +347,6 @@ __device__ void batch_problem(const BatchArgs &a, int b, double *sm, BatchLds &L
     double *P = a.Pbuf + pr.P_off;
     double *Y = a.Ybuf + pr.Y_off;
     const double *mu = a.mu + (int64_t)pr.set * n;
-    const int4 *tiles = a.tiles + st.tile_off;
     const float4 *wt = a.w + st.tile_off * (kTileElems / 4);
     const bool vp = (n & 1) == 0;
     // coarse error bound |r~ - r| <= e_abs + e_rel r: the FP64 product's
@@ -351,37 +370,51 @@ __device__ void batch_problem(const BatchArgs &a, int b, double *sm, BatchLds &L
             batch_gemm16<TX, KP>(X, a.ldx, idx, M, n, mu, P, Y, slab * 16, a.vx, vp);
         if (threadIdx.x == 0) s_run = kKeyNone;
         __syncthreads();
-        // pass: wavefront wv takes quarter tiles wv, wv + 4, ...
+        // pass: wavefront wv takes quarter tiles wv, wv + 4, ...; the loads of
+        // the next item are issued before the current item's arithmetic, and
+        // every load of an item is independent (tile coordinates computed,
+        // not loaded)
         WaveBest wb{__builtin_huge_val(), __builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0};
         CandList cl{s_cij[wv], s_ckey[wv], 0, a.cap, 0, kKeyNone};
         uint32_t kmin = kKeyNone;
         double *yl = s_y[wv];
-        for (int64_t h = wv; h < nitem; h += kPairBlock / kWave) {
-            const int64_t t = h >> 2;
-            const int q = (int)(h & 3);
-            const int4 tb = tiles[t];
-            const float4 *tp = wt + t * (kTileElems / 4) + q * 256 + lane;
+        struct ItemLoads {
             float4 w4[4];
-#pragma unroll
-            for (int g = 0; g < 4; ++g) w4[g] = tp[g * 64];
-            const int32_t row0 = tb.x * kTile + 16 * q, col = tb.y * kTile + lane;
-            const double *ysrc = Y + (int64_t)row0 * KP;
             double yr[NY];
-#pragma unroll
-            for (int u = 0; u < NY; ++u) {
-                const int f = lane + u * kWave;
-                yr[u] = ysrc[f < 16 * KP ? f : 0];
-            }
             double yj[KP];
+            int32_t row0, col;
+        };
+        auto fetch = [&](int64_t hh, ItemLoads &L) __attribute__((always_inline)) {
+            const int64_t t = hh >> 2;
+            const int q = (int)(hh & 3);
+            const int2 tc = tile_of_index(t, st.nb);
+            const float4 *tp = wt + t * (kTileElems / 4) + q * 256 + lane;
 #pragma unroll
-            for (int c = 0; c < KP; ++c) yj[c] = Y[(int64_t)col * KP + c];
+            for (int g = 0; g < 4; ++g) L.w4[g] = tp[g * 64];
+            L.row0 = tc.x * kTile + 16 * q;
+            L.col = tc.y * kTile + lane;
+            const double *ysrc = Y + (int64_t)L.row0 * KP;
+#pragma unroll
+            for (int u = 0; u < NY; ++u) {
+                const int f = lane + u * kWave;
+                L.yr[u] = ysrc[f < 16 * KP ? f : 0];
+            }
+#pragma unroll
+            for (int c = 0; c < KP; ++c) L.yj[c] = Y[(int64_t)L.col * KP + c];
+        };
+        ItemLoads cur, nxt;
+        int64_t h = wv;
+        if (h < nitem) fetch(h, cur);
+        nxt = cur;
+        for (; h < nitem; h += kPairBlock / kWave) {
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int u = 0; u < NY; ++u) {
                 const int f = lane + u * kWave;
-                if (f < 16 * KP) yl[f] = yr[u];
+                if (f < 16 * KP) yl[f] = cur.yr[u];
             }
             __builtin_amdgcn_wave_barrier();
+            if (h + kPairBlock / kWave < nitem) fetch(h + kPairBlock / kWave, nxt);
             uint32_t key[16];
             uint32_t lmin = kKeyNone;
 #pragma unroll
@@ -390,10 +423,10 @@ __device__ void batch_problem(const BatchArgs &a, int b, double *sm, BatchLds &L
                 double acc = 0.0;
 #pragma unroll
                 for (int c = 0; c < KP; ++c) {
-                    const double d = yi[c] - yj[c];
+                    const double d = yi[c] - cur.yj[c];
                     acc = __builtin_fma(d, d, acc);
                 }
-                const float4 &wg = w4[e >> 2];
+                const float4 &wg = cur.w4[e >> 2];
                 const float wv4 = (e & 3) == 0 ? wg.x : (e & 3) == 1 ? wg.y : (e & 3) == 2 ? wg.z : wg.w;
                 key[e] = __float_as_uint((float)(acc * (double)wv4));
                 lmin = min(lmin, key[e]);
@@ -401,6 +434,7 @@ __device__ void batch_problem(const BatchArgs &a, int b, double *sm, BatchLds &L
             const uint32_t m = wave_min_u32_fast(lmin);
             kmin = min(kmin, m);
             const uint32_t T2 = item_window(block_run_min(&s_run, m), wa, wbb);
+            const int32_t row0 = cur.row0, col = cur.col;
             if (m <= T2)
                 emit_cands(cl, key, lmin, T2,
                            [=](int e, int32_t &i, int32_t &j) __attribute__((always_inline)) {
@@ -409,6 +443,7 @@ __device__ void batch_problem(const BatchArgs &a, int b, double *sm, BatchLds &L
                            },
                            wb);
             __builtin_amdgcn_wave_barrier();
+            cur = nxt;
         }
         // rescore the window pairs in FP64 from X
         {
