@@ -41,6 +41,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0                  # MI355X HBM3E
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: lane-instructions/s (FP32 or FP64)
+MFMA_F64_TFLOPS = 78.6                 # MI355X dense FP64 matrix peak
 
 
 def log(msg):
@@ -49,7 +50,8 @@ def log(msg):
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pass_fused_trig64_N4000_n64_k6_traffic.txt")
 KERNEL_SOURCES = ("paper_1807_03425_amd/csrc/sap_iter.hip", "paper_1807_03425_amd/csrc/sap_common.h",
-                  "paper_1807_03425_amd/csrc/sap_api.hip")
+                  "paper_1807_03425_amd/csrc/sap_api.hip", "paper_1807_03425_amd/csrc/sap_kinst.hip",
+                  "paper_1807_03425_amd/csrc/sap_launch.h")
 
 
 def measured_traffic():
@@ -149,16 +151,23 @@ def sap_leg(torch, np, w, form, steps, warmup, gemm="f64", prof_steps=None, keep
 
 
 def softmin_slots(K):
-    """Issue slots per pair of the soft-min passes, counting the method's own
-    work (a transcendental -- sqrt, rsq, exp2 -- as 4):
+    """Vector issue slots per pair of the soft-min passes, counting the
+    method's own work (a transcendental -- sqrt, rsq, exp2 -- as 4):
       forward:  K subtractions + K FMAs (||y_i - y_j||^2), a multiply by
                 1/d^2, a select of masked pairs, sqrt, min, and for the sum
                 an FMA, exp2 and an add: 2K + 14;
-      backward: the same 2K for the norm, multiply, rsq, multiply, FMA,
-                exp2, two multiplies, two compares and a select for the
-                weight, and the contraction's two accumulations (z_j and
-                z_i, K FMAs each): 4K + 16."""
-    return 2 * K + 14, 4 * K + 16
+      backward: the same 2K for the norm, then multiply, rsq, multiply,
+                FMA, exp2, two multiplies, two compares and a select for the
+                weight, and the column side's K FMAs (z_j += a (y_j - y_i)):
+                3K + 16.  The row side's contraction sum_j a_ij y_j (2K flops
+                per pair) runs on the FP64 matrix cores and is priced there
+                (softmin_bwd_flops)."""
+    return 2 * K + 14, 3 * K + 16
+
+
+def softmin_bwd_flops(K):
+    """FP64 matrix-core flops per pair of the backward's row-side contraction."""
+    return 2 * K
 
 
 def softmin_leg(torch, np, w, tau, steps, warmup, adam=True):
@@ -220,6 +229,10 @@ def softmin_leg(torch, np, w, tau, steps, warmup, adam=True):
             out[f"roofline_{slot}"] = dict(bound="alu", achieved=ach / 1e12, peak=VALU_LANE_OPS / 1e12,
                                            unit="T lane-instr/s", frac=ach / VALU_LANE_OPS,
                                            slots_per_pair=slots, traffic=None)
+    if "sm_bwd" in kern:
+        fl = softmin_bwd_flops(w.k) * pairs / (kern["sm_bwd"] / 1e3)
+        out["mfma_sm_bwd"] = dict(bound="mfma", achieved=fl / 1e12, peak=MFMA_F64_TFLOPS, unit="TFLOP/s",
+                                  frac=fl / 1e12 / MFMA_F64_TFLOPS, flops_per_pair=softmin_bwd_flops(w.k))
     return out
 
 
@@ -280,6 +293,9 @@ def main():
                     help="budget of the FP64 CPU oracle baseline (0 disables it)")
     ap.add_argument("--softmin-steps", type=int, default=20,
                     help="timed soft-min optimisation steps on the hyperspectral workload")
+    ap.add_argument("--gemms", default="bf16,f64",
+                    help="Y GEMMs of the blob and torus legs (comma list of bf16, f32, f64)")
+    ap.add_argument("--blob-ks", default="2,4,8", help="projection dimensions of the blob leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-MiB device buffer 3 times (a kernel of known traffic, "
                          "to scale rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -388,13 +404,14 @@ def main():
             line["fused_over_plain"] = res["fused"]["secants_per_s"] / res["plain"]["secants_per_s"]
 
     legs = [l for l in args.legs.split(",") if l]
+    gemms = [g for g in args.gemms.split(",") if g]
     if "trig10" in legs:
         log("leg trig10 (paper Sec. 5 curve, plain FP64, 200 iterations)")
         line["trig10"] = sap_leg(torch, np, sap_inputs.make("trig10"), "plain", 200, 5)
     if "blob" in legs:
         line["blob"] = {}
-        for k in (2, 4, 8):
-            for g in ("bf16", "f64"):
+        for k in [int(v) for v in args.blob_ks.split(",") if v]:
+            for g in gemms:
                 log(f"leg blob k={k} (fused, {g} Y GEMM, 300 iterations)")
                 line["blob"][f"k{k}_{g}"] = sap_leg(torch, np, sap_inputs.make("blob", k=k), "fused", 300, 5,
                                                     gemm=g)
@@ -405,7 +422,7 @@ def main():
     if "torus" in legs:
         wt = sap_inputs.make("torus")
         line["torus"] = {}
-        for g in ("bf16", "f64"):
+        for g in gemms:
             log(f"leg torus: fused iterations, {g} Y GEMM")
             line["torus"][f"iterations_{g}"] = sap_leg(torch, np, wt, "fused", 100, 3, gemm=g, prof_steps=20)
         log("leg torus: soft-min fwd + bwd")

@@ -26,6 +26,9 @@
 using namespace sap;
 
 // Grid sizing of the fused pass: short pairs per short-pair block.
+#ifndef SAP_SHORT64_PER_BLOCK
+#define SAP_SHORT64_PER_BLOCK 256   // short pairs per block when their bounds come from the FP64 Y
+#endif
 #ifndef SAP_SHORT_PER_BLOCK
 #define SAP_SHORT_PER_BLOCK 64
 #endif
@@ -61,6 +64,8 @@ struct sap_ctx {
     int2 *d_tiles = nullptr;
     float4 *d_invd2 = nullptr;
     float *d_Y = nullptr;
+    double *d_Y64 = nullptr;  // FP64 GEMM with short pairs: the unrounded Y
+    double s_d2 = 0, s_eps = 0;   // short-pair bound from d_Y64
     int2 *d_close = nullptr;
     double *d_cd = nullptr;   // short pairs: ||x_i - x_j||
     // the short-pair list (sorted by (i, j)) as CSR by i and by j
@@ -79,6 +84,7 @@ struct sap_ctx {
     Partial *d_part = nullptr;   // pass-block results, then one per short-pair block
     DevResult *d_res = nullptr;
     int pass_grid = 0, short_grid = 0;
+    int short_grid_it = 0;   // short-pair blocks of the iteration's pass (<= short_grid)
     int sm_grid = 0;   // fused: blocks of the soft-min tile passes
     size_t tail_lds = 0;
 
@@ -452,6 +458,16 @@ static sap_status init_fused(sap_ctx *h) {
     // iteration: 64 short pairs per block (16 per wavefront, on the matrix
     // cores); the soft-min's short-pair blocks use the same grid size
     h->short_grid = h->nclose > 0 ? (int)std::min<int64_t>(ceil_div(h->nclose, SAP_SHORT_PER_BLOCK), 1024) : 0;
+    h->short_grid_it = h->short_grid;
+    // FP64 GEMM: the iteration bounds each short pair from the unrounded Y
+    // (error 2 delta64 / d, delta64 = 4 (n + 2) sqrt(k) u64 R) and evaluates
+    // exactly only those that may hold one of its block's two smallest values
+    if (h->nclose > 0 && h->cfg.gemm == SAP_GEMM_F64) {
+        SAP_TRY(dalloc(h, &h->d_Y64, sizeof(double) * (size_t)h->Npad * h->kp));
+        h->s_d2 = 2.0 * h->radius * (h->n + 2) * sk * kU64 * 4.0 * (1.0 + 1e-6);
+        h->s_eps = 2.0 * (h->n + h->k + 12) * kU64;
+        h->short_grid_it = (int)std::min<int64_t>(ceil_div(h->nclose, SAP_SHORT64_PER_BLOCK), 1024);
+    }
     // pass blocks: with the short-pair blocks, one round of resident blocks
     // (four per compute unit), and at least one half-tile per wavefront; the
     // blocks stride over the rest of the tiles
@@ -460,7 +476,7 @@ static sap_status init_fused(sap_ctx *h) {
         cus = 256;
     const int64_t slots = 4 * (int64_t)cus;
     h->pass_grid = (int)std::max<int64_t>(
-        1, std::min<int64_t>(ceil_div(2 * h->ntiles, 4), std::max<int64_t>(slots / 4, slots - h->short_grid)));
+        1, std::min<int64_t>(ceil_div(2 * h->ntiles, 4), std::max<int64_t>(slots / 4, slots - h->short_grid_it)));
     // soft-min tile passes (three or four blocks per compute unit): eight
     // half-tiles per block, many rounds
     h->sm_grid = (int)std::min<int64_t>(ceil_div(2 * h->ntiles, 8), 8192);
@@ -527,6 +543,9 @@ static SweepArgs<TX> sweep_args(sap_ctx *h, double *tr_min, int64_t *tr_ij, int3
     a.close = h->d_close;
     a.cd = h->d_cd;
     a.nclose = h->nclose;
+    a.Y64 = h->d_Y64;
+    a.s_d2 = h->s_d2;
+    a.s_eps = h->s_eps;
     a.part = h->d_part;
     a.e_abs = h->e_abs;
     a.e_rel = h->e_rel;
@@ -567,7 +586,7 @@ static sap_status launch_pass(sap_ctx *h) {
     const int K = h->k;
     const bool fused = h->cfg.form == SAP_FUSED;
     const SweepArgs<TX> a = sweep_args<TX>(h, nullptr, nullptr, nullptr, 0);
-    const int nshort = fused ? h->short_grid : 0;
+    const int nshort = fused ? h->short_grid_it : 0;
     const dim3 g1((unsigned)(h->pass_grid + nshort)), blk(kPairBlock);
     SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 1, "k_pass", g1, blk, 0, [&](const LaunchCfg &c) {
         return KLaunch<K, TX>::pass(c, fused, a, nshort);
@@ -581,7 +600,7 @@ static sap_status launch_select(sap_ctx *h, int do_step, double *tr_min, int64_t
     const int K = h->k;
     const bool fused = h->cfg.form == SAP_FUSED;
     const SweepArgs<TX> a = sweep_args<TX>(h, tr_min, tr_ij, tr_cert, it);
-    const int nshort = fused ? h->short_grid : 0;
+    const int nshort = fused ? h->short_grid_it : 0;
     const int pr_kind = fused ? 0 : (h->cfg.dtype == SAP_F64 ? 2 : 1);
     const uint32_t lds = (uint32_t)h->tail_lds;
     const dim3 blk(kPairBlock);
@@ -602,7 +621,7 @@ static sap_status launch_selprep(sap_ctx *h, double *tr_min, int64_t *tr_ij, int
     const dim3 g0((unsigned)(h->Npad / 64)), blk(kPairBlock);
     SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 6, "k_selprep", g0, blk, (uint32_t)h->tail_lds,
                                           [&](const LaunchCfg &c) {
-        return KLaunch<K, TX>::selprep(c, a, h->short_grid, h->d_P64t_alt, h->cfg.alpha, h->cfg.rule,
+        return KLaunch<K, TX>::selprep(c, a, h->short_grid_it, h->d_P64t_alt, h->cfg.alpha, h->cfg.rule,
                                        h->d_mu, h->d_Y, h->Npad);
     })));
     std::swap(h->d_P64t, h->d_P64t_alt);
@@ -625,7 +644,7 @@ static sap_status launch_iteration(sap_ctx *h, int do_step, double *tr_min, int6
 // per iteration) keep the three launches.
 template <typename TX>
 static sap_status launch_run(sap_ctx *h, int32_t iters, double *tr_min, int64_t *tr_ij, int32_t *tr_cert) {
-    const int64_t reads = (h->Npad / 64) * (int64_t)(h->pass_grid + h->short_grid) * (int64_t)sizeof(Partial);
+    const int64_t reads = (h->Npad / 64) * (int64_t)(h->pass_grid + h->short_grid_it) * (int64_t)sizeof(Partial);
     if (h->cfg.form != SAP_FUSED || reads > (16 << 20)) {
         for (int32_t it = 0; it <= iters; ++it)
             SAP_TRY(launch_iteration<TX>(h, it < iters ? 1 : 0, tr_min, tr_ij, tr_cert, it));
@@ -773,8 +792,7 @@ static sap_status sm_backward(sap_ctx *h, double tau, const float *grad_loss, fl
                                           [&](const LaunchCfg &c) {
         return KLaunch<K, TX>::sm_zred(c, a, h->nb, h->N, h->d_rp_i, h->d_rp_j, h->d_permj, h->d_smZ);
     })));
-    const unsigned slices = (unsigned)ceil_div((int64_t)h->n * K, 256);
-    SAP_TRY(launch(h, 5, "k_sm_grad", k_sm_grad<TX>, dim3((unsigned)h->sm_chunks, slices), dim3(256), 0,
+    SAP_TRY(launch(h, 5, "k_sm_grad", k_sm_grad<TX>, dim3((unsigned)h->sm_chunks), dim3(256), 0,
                    X, h->ldx, h->N, h->n, K, (const double *)h->d_mu, (const double *)h->d_smZ,
                    h->sm_rows, h->d_smG));
     SAP_TRY(launch(h, 5, "k_sm_dP", k_sm_dP, dim3((unsigned)ceil_div((int64_t)h->n * K, 64)), dim3(256), 0,

@@ -118,6 +118,27 @@ __device__ __forceinline__ void load16(const double *__restrict__ p, bool vec, d
     }
 }
 
+// 16 consecutive elements in their own type (a prefetch: converted at use,
+// so that no conversion waits for the load where it is issued).
+template <typename T>
+__device__ __forceinline__ void load16_raw(const T *__restrict__ p, bool vec, T (&o)[16]) {
+    if (vec) {
+        using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+        constexpr int W = 16 / (int)sizeof(T);
+        const V *q = reinterpret_cast<const V *>(p);
+#pragma unroll
+        for (int u = 0; u < 16 / W; ++u) {
+            const V t = q[u];
+            const T *tv = reinterpret_cast<const T *>(&t);
+#pragma unroll
+            for (int w = 0; w < W; ++w) o[W * u + w] = tv[w];
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) o[u] = p[u];
+    }
+}
+
 // Y[r][c] = fl32( sum_l (x_rl - mu_l) P_lc ), rows >= N and columns >= k set
 // to 0.  One wavefront per 16-row block; v_mfma_f64_16x16x4_f64 with
 //   A (16 x 4):  lane = row + 16 * kk   (row = lane % 16, kk = lane / 16)
@@ -237,12 +258,13 @@ __device__ __forceinline__ void gemm_block_lowp(const TX *__restrict__ X, int64_
 
 // x0, m0 (used when use_x0): the first chunk's X values and means, loaded
 // earlier by gemm_first_x.  gemm: SAP_GEMM_F64 (below), or SAP_GEMM_F32 /
-// SAP_GEMM_BF16 (gemm_block_lowp).
+// SAP_GEMM_BF16 (gemm_block_lowp).  With the FP64 GEMM, Y64 (if not null)
+// receives the same products unrounded (the short-pair bounds use them).
 template <typename TX>
 __device__ __forceinline__ void gemm_block(const TX *__restrict__ X, int64_t ldx, int64_t N, int n, int k,
                            const double *__restrict__ mu, const double *__restrict__ P64t,
-                           float *__restrict__ Y, int kp, int64_t Npad, bool vx, bool vp,
-                           const double (&x0)[16], const double (&m0)[16], bool use_x0, int gemm) {
+                           float *__restrict__ Y, double *__restrict__ Y64, int kp, int64_t Npad, bool vx,
+                           bool vp, const double (&x0)[16], const double (&m0)[16], bool use_x0, int gemm) {
     const int lane = threadIdx.x & 63;
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
     if (row0 >= Npad) return;
@@ -261,21 +283,37 @@ __device__ __forceinline__ void gemm_block(const TX *__restrict__ X, int64_t ldx
     const double *pc = P64t + (int64_t)(m < k ? m : k - 1) * n;
     double4_t acc = {0.0, 0.0, 0.0, 0.0};
     int l0 = 0;
-    for (; l0 + 64 <= n; l0 += 64) {
+    if (n >= 64) {
+        // software-pipelined over 64-component chunks: the next chunk's
+        // operands are in flight during this chunk's 16 MFMAs
         double xa[16], ma[16], pb[16];
-        const int lb = l0 + 16 * kk;
-        if (use_x0 && l0 == 0) {
+        if (use_x0) {
 #pragma unroll
             for (int u = 0; u < 16; ++u) { xa[u] = x0[u]; ma[u] = m0[u]; }
         } else {
-            load16(xr + lb, vx, xa);
-            load16(mu + lb, true, ma);
+            load16(xr + 16 * kk, vx, xa);
+            load16(mu + 16 * kk, true, ma);
         }
-        load16(pc + lb, vp, pb);
+        load16(pc + 16 * kk, vp, pb);
+        for (; l0 + 64 <= n; l0 += 64) {
+            TX xn[16];
+            double mn[16], pn[16];
+            const bool more = l0 + 128 <= n;           // wavefront-uniform
+            if (more) {
+                const int lb = l0 + 64 + 16 * kk;
+                load16_raw(xr + lb, vx, xn);
+                load16_raw(mu + lb, true, mn);
+                load16_raw(pc + lb, vp, pn);
+            }
 #pragma unroll
-        for (int s = 0; s < 16; ++s)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64((xa[s] - ma[s]) * rmask, pb[s] * pmask,
-                                                       acc, 0, 0, 0);
+            for (int s = 0; s < 16; ++s)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64((xa[s] - ma[s]) * rmask, pb[s] * pmask,
+                                                           acc, 0, 0, 0);
+            if (more) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u) { xa[u] = (double)xn[u]; ma[u] = mn[u]; pb[u] = pn[u]; }
+            }
+        }
     }
     for (; l0 < n; l0 += 4) {
         const int l = l0 + kk;
@@ -290,7 +328,9 @@ __device__ __forceinline__ void gemm_block(const TX *__restrict__ X, int64_t ldx
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t r = row0 + kk + 4 * v;
-            Y[r * kp + m] = (r < N && m < k) ? (float)acc[v] : 0.0f;
+            const double y = (r < N && m < k) ? acc[v] : 0.0;
+            Y[r * kp + m] = (float)y;
+            if (Y64) Y64[r * kp + m] = y;
         }
     }
 }
@@ -606,6 +646,8 @@ struct SweepArgs {
     const int2 *close;    // short pairs (i, j), sorted
     const double *cd;     // their lengths ||x_i - x_j||
     int64_t nclose;
+    double *Y64;          // FP64 Y (FP64 GEMM; null otherwise): short-pair bounds
+    double s_d2, s_eps;   // short-pair bound: |r~ - r| <= s_d2 / d + s_eps r~
     // FP64 rescoring and selection
     double e_abs, e_rel;
     float wa, wb;         // item_window coefficients: (1 + e_rel)/(1 - e_rel), 2 e_abs/(1 - e_rel),
@@ -1053,6 +1095,112 @@ __device__ void short_block(const SweepArgs<TX> &a, int sb, int nshort) {
     block_reduce_partial(best, bi, bj, second, cnt, 0, 0, kKeyNone, kKeyNone, a.part + a.npass + sb);
 }
 
+// Bounds of one short pair's value from the unrounded projection Y64:
+// r~ = ||y64_i - y64_j|| / d with |r~ - r| <= s_d2 / d + s_eps r~ (each
+// row of Y64 is within delta64 = 4 (n + 2) sqrt(k) u64 R of its exact value,
+// s_d2 = 2 delta64; s_eps covers the rounding of the difference, the norm,
+// the division and of d itself).
+template <int K, typename TX>
+__device__ __forceinline__ void short_bounds(const SweepArgs<TX> &a, int64_t e, double &lb, double &ub) {
+    const int2 pr = a.close[e];
+    const double d = a.cd[e];
+    const double *yi = a.Y64 + (int64_t)pr.x * a.kp;
+    const double *yj = a.Y64 + (int64_t)pr.y * a.kp;
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const double t = yi[c] - yj[c];
+        s = __builtin_fma(t, t, s);
+    }
+    const double rt = sqrt(s) / d;
+    const double eb = a.s_d2 / d + a.s_eps * rt;
+    lb = rt - eb;
+    ub = rt + eb;
+}
+
+// (u1 <= u2) <- the two smallest of {u1, u2, v1, v2} (two sorted pairs of
+// values of distinct pairs).
+__device__ __forceinline__ void min2_merge(double &u1, double &u2, double v1, double v2) {
+    const double s = fmin(fmax(u1, v1), fmin(u2, v2));
+    u1 = fmin(u1, v1);
+    u2 = s;
+}
+
+// Short pairs of the iteration from the FP64 Y, then exactly (FP64 GEMM).
+// The block takes a contiguous range of the list.  First every pair's
+// bounds [r~ - e, r~ + e]; U2 = the second-smallest upper bound, so at least
+// two of the block's pairs are worth at most U2.  Then every pair with
+// r~ - e <= U2 is evaluated exactly from X (short_c16, 16 per wavefront step;
+// the candidates of a 64-pair chunk are compacted through LDS).  A pair left
+// out is worth more than U2, hence more than the block's two smallest
+// values, which are therefore exact FP64 evaluations, as with every pair
+// evaluated exactly.
+template <int K, typename TX>
+__device__ void short_block_y64(const SweepArgs<TX> &a, int sb, int nshort) {
+    __shared__ int32_t s_cidx[kPairBlock / kWave][kWave];
+    __shared__ double s_u[kPairBlock / kWave][2];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, kk = lane >> 4;
+    const int64_t per = (a.nclose + nshort - 1) / nshort;
+    const int64_t e0 = (int64_t)sb * per;
+    const int64_t e1 = e0 + per < a.nclose ? e0 + per : a.nclose;
+    const double inf = __builtin_huge_val();
+    double u1 = inf, u2 = inf;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kPairBlock) {
+        double lb, ub;
+        short_bounds<K, TX>(a, e, lb, ub);
+        min2_merge(u1, u2, ub, inf);
+    }
+#pragma unroll 1
+    for (int o = 32; o > 0; o >>= 1) {
+        const double v1 = __shfl_xor(u1, o, kWave), v2 = __shfl_xor(u2, o, kWave);
+        min2_merge(u1, u2, v1, v2);
+    }
+    if (lane == 0) { s_u[wv][0] = u1; s_u[wv][1] = u2; }
+    __syncthreads();
+    double U1 = s_u[0][0], U2 = s_u[0][1];
+#pragma unroll
+    for (int w = 1; w < kPairBlock / kWave; ++w) min2_merge(U1, U2, s_u[w][0], s_u[w][1]);
+    double best = inf, second = inf;
+    int32_t bi = 0x7fffffff, bj = 0x7fffffff, cnt = 0;
+    for (int64_t c0 = e0 + (int64_t)wv * kWave; c0 < e1; c0 += kPairBlock) {
+        const int64_t e = c0 + lane;
+        bool cand = false;
+        if (e < e1) {
+            double lb, ub;
+            short_bounds<K, TX>(a, e, lb, ub);
+            cand = !(lb > U2);
+        }
+        const uint64_t mask = __ballot(cand);
+        const int ncand = __popcll(mask);
+        if (cand)
+            s_cidx[wv][__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] = lane;
+        __builtin_amdgcn_wave_barrier();
+        for (int g = 0; g < ncand; g += 16) {
+            const int slot = g + m;
+            const bool rin = slot < ncand;
+            const int64_t ee = c0 + s_cidx[wv][rin ? slot : g];
+            const int2 pr = a.close[ee];
+            const double dlen = a.cd[ee];
+            const double4_t acc = short_c16<K, TX>(a.X, a.ldx, pr, rin, a.n, a.P64t, a.vx, a.vp);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double q2 = row_sum16(acc[v] * acc[v]);
+                const int src = kk + 4 * v;          // the lane (m = src) that loaded this pair
+                const int pi = __shfl(pr.x, src, kWave), pj = __shfl(pr.y, src, kWave);
+                const double dv = __shfl(dlen, src, kWave);
+                if (m == 0 && g + src < ncand) {
+                    ++cnt;
+                    lex_pick2(best, bi, bj, second, sqrt(q2) / dv, pi, pj, inf);
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    block_reduce_partial(best, bi, bj, second, cnt, 0, 0, kKeyNone, kKeyNone, a.part + a.npass + sb);
+}
+
 // Selection (one block, after the pass): the lexicographic minimum of every
 // pass block's and short-pair block's FP64 result, the record, and the
 // coarse minimum with its window (reported).  Eight partials per thread are
@@ -1150,7 +1298,8 @@ template <int K, typename TX, bool FUSED>
 __global__ __launch_bounds__(kPairBlock, (FUSED || sizeof(TX) == 4 || K <= 12) ? 4 : 3) void k_pass(SweepArgs<TX> a, int nshort) {
     if constexpr (FUSED) {
         if ((int)blockIdx.x < nshort) {
-            short_block<K, TX>(a, (int)blockIdx.x, nshort);
+            if (a.Y64) short_block_y64<K, TX>(a, (int)blockIdx.x, nshort);
+            else short_block<K, TX>(a, (int)blockIdx.x, nshort);
             return;
         }
     }
@@ -1164,7 +1313,8 @@ template <int K, typename TX>
 __global__ __launch_bounds__(kPairBlock) void k_prep(SweepArgs<TX> a, const double *__restrict__ mu,
                                                      float *__restrict__ Y, int64_t Npad) {
     const double none[16] = {};
-    gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, a.P64t, Y, a.kp, Npad, a.vx, a.vp, none, none, false, a.gemm);
+    gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, a.P64t, Y, a.Y64, a.kp, Npad, a.vx, a.vp, none, none, false,
+                   a.gemm);
 }
 
 // ------------------------------------------------------------------ the update
@@ -1598,8 +1748,8 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
         for (int e = threadIdx.x; e < K * a.n; e += kPairBlock) Pn[e] = sm_sp[e];   // P unchanged
     }
     __syncthreads();
-    gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, sm_sp, Y, a.kp, Npad, a.vx, (a.n & 1) == 0, x0, m0, a.n >= 64,
-                   a.gemm);
+    gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, sm_sp, Y, a.Y64, a.kp, Npad, a.vx, (a.n & 1) == 0, x0, m0,
+                   a.n >= 64, a.gemm);
 }
 
 #ifndef SAP_KINST   // K-independent kernels: compiled once, in the host runtime unit

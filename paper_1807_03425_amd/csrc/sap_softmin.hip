@@ -22,9 +22,11 @@
 //             k_sm_fwd     per-block (min, scaled sum) over the tiles
 //             k_sm_fin     one block: merge in FP64, L, loss
 //   backward: k_sm_prep    (short-pair blocks only) a_ij (y_i - y_j) per short pair
-//             k_sm_bwd     per half-tile partial z sums: rows and columns
+//             k_sm_bwd     per half-tile partial z sums, rows and columns
+//                          (weights and column side on VALU, row-side
+//                          contraction on FP64 MFMA)
 //             k_sm_zred    z_i per point: tile partials + short pairs, FP64
-//             k_sm_grad    (X - mu)^T Z per row chunk, FP64
+//             k_sm_grad    (X - mu)^T Z per row chunk, FP64 MFMA
 //             k_sm_dP      sum of the chunks times dL/dloss
 #include "sap_common.h"
 
@@ -57,8 +59,8 @@ struct SmArgs {
     SmPart *part;          // npass + nshort partials (forward)
     const double *Lp;      // L of the forward (backward)
     // backward partials
-    float *Zr;             // per half-tile: K x 32 row sums
-    float *Zc;             // per half-tile: K x 64 column sums
+    float *Zr;             // per half-tile: 32 x K row-side partials, point-major
+    float *Zc;             // per half-tile: 64 x K column-side partials, point-major
     double *zpair;         // per short pair: a (y_i - y_j), K values
 };
 
@@ -150,7 +152,8 @@ __global__ __launch_bounds__(kPairBlock) void k_sm_prep(SmArgs a, const TX *__re
     if ((int)blockIdx.x < gemm_blocks)
     {
         const double none[16] = {};
-        gemm_block<TX>(X, ldx, N, a.n, K, mu, a.P64t, Y, a.kp, Npad, a.vx, a.vp, none, none, false, a.gemm);
+        gemm_block<TX>(X, ldx, N, a.n, K, mu, a.P64t, Y, nullptr, a.kp, Npad, a.vx, a.vp, none, none, false,
+                       a.gemm);
     }
     else
         sm_short_block<K, TX>(a, X, ldx, (int)blockIdx.x - gemm_blocks, (int)gridDim.x - gemm_blocks,
@@ -241,33 +244,52 @@ __global__ __launch_bounds__(kPairBlock) void k_sm_fin(const SmPart *__restrict_
 
 #endif
 
-// Backward pass: one wavefront per half-tile (rows i = 64 bi + 32 half + 0..31,
-// columns j = 64 bj + lane).  Phase 1 (lane = column): a_ij and the column
-// sums  z_j -= a_ij (y_i - y_j); a_ij goes to the wavefront's LDS block (row
-// stride 65: conflict-free both ways).  Phase 2 (lane = row i = lane % 32,
-// column half lane / 32): z_i += a_ij (y_i - y_j) over its 32 columns, then the
-// two halves are added.  Partials go to Zr / Zc, component-major per half-tile.
-// LDS sized for K's padded row length: 37.9 KB (K <= 4) to 57.9 KB (K >= 13)
-// per block.  Three blocks (three wavefronts per SIMD, at most 168 registers)
-// fit a compute unit's 160 KB for K <= 12; two for K >= 13, which then keep
-// up to 256 registers.
+// Row stride of a wavefront's 32 x 64 weight block in LDS.  66 = 2 mod 32
+// words: the row contraction's reads (16 rows x 4 consecutive columns) meet
+// every bank once per half-wavefront, and the phase-1 writes (one row, 64
+// consecutive columns) too.
+constexpr int kAStride = 66;
+
+// Backward pass: one wavefront per half-tile (rows i = 64 bi + 32 half +
+// 0..31, columns j = 64 bj + 0..63).
+// Phase 1 (lane = column j): the weights a_ij of the lane's column, one
+// float4 of 1/d^2 per four rows, and the column side
+//   z_j += sum_i a_ij (y_j - y_i)
+// accumulated in FP32 from the differences y_i - y_j that the weight needed
+// anyway; a_ij goes to the wavefront's LDS block.
+// Phase 2: the row side
+//   z_i += sum_j a_ij (y_i - y_j) = (sum_j a_ij) y_i - (A Y_J)_i
+// on the matrix cores in FP64 (v_mfma_f64_16x16x4f64, K padded to 16
+// columns): lane (c16 = lane % 16, r4 = lane / 16) feeds A = a[16 mb + c16]
+// [4 t + r4] from LDS and B = y_J[4 t + r4][c16].  The FP32 weights and
+// coordinates are exact in FP64 and the products and sums FP64, so the
+// difference of the two large terms keeps the accuracy of the direct sum of
+// differences.  For K < 16 the padding column 15 of B is 1, which makes
+// column 15 of the product the row sum; K = 16 sums the rows separately.
+// Partials go to Zr (32 x K) and Zc (64 x K) per half-tile, point-major, in
+// FP32.  LDS per block: 38 KB (K <= 4) to 56 KB (K >= 13): three blocks per
+// compute unit for K <= 12 (at most 168 registers), two for K >= 13.
 template <int K>
 __global__ __launch_bounds__(kPairBlock, K <= 12 ? 3 : 2) void k_sm_bwd(SmArgs a) {
     constexpr int KP = K <= 4 ? 4 : (K <= 8 ? 8 : (K <= 12 ? 12 : 16));   // the Y row length kp
     __shared__ float4 s_y[kPairBlock / kWave][32 * KP / 4];
     __shared__ float4 s_yc[kPairBlock / kWave][64 * KP / 4];
-    __shared__ float s_a[kPairBlock / kWave][32 * 65];
+    __shared__ float s_a[kPairBlock / kWave][32 * kAStride];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t wid = (int64_t)blockIdx.x * (kPairBlock / kWave) + wv;
     const int64_t nw = (int64_t)a.npass * (kPairBlock / kWave);
-    const int kp = a.kp;
+    constexpr int kp = KP;                            // equals a.kp
     const float c2 = a.c2;
     const float Lc = (float)(*a.Lp) * c2;
     float4 *yl = s_y[wv];
     float4 *ycl = s_yc[wv];
     float *al = s_a[wv];
-    const int ri = lane & 31, hh = lane >> 5;
+    const int c16 = lane & 15, r4 = lane >> 4;
+    const bool qin = c16 < K;
+    const int qc = qin ? c16 : K - 1;                 // clamped component: in-bounds LDS reads
+    const double bpad = (K < 16 && c16 == 15) ? 1.0 : 0.0;
+    const float *alr = al + c16 * kAStride + r4;      // row-side reads: + 16 mb kAStride + 4 tt
     for (int64_t h = wid; h < a.nhalf; h += nw) {
         const int64_t t = h >> 1;
         const int half = (int)(h & 1);
@@ -281,12 +303,11 @@ __global__ __launch_bounds__(kPairBlock, K <= 12 ? 3 : 2) void k_sm_bwd(SmArgs a
         for (int f = lane; f < 8 * kp; f += kWave) yl[f] = ysrc[f];
         for (int f = lane; f < 16 * kp; f += kWave) ycl[f] = ycsrc[f];
         __builtin_amdgcn_wave_barrier();
-        float yj[K];
-        load_yj<K>(a.Y, kp, (int64_t)b.y * kTile + lane, yj);
         const float *yi0 = reinterpret_cast<const float *>(yl);
-        float zc[K];
+        const float *yc0 = reinterpret_cast<const float *>(ycl);
+        float yj[K], zc[K];
 #pragma unroll
-        for (int q = 0; q < K; ++q) zc[q] = 0.0f;
+        for (int q = 0; q < K; ++q) { yj[q] = yc0[lane * kp + q]; zc[q] = 0.0f; }
         // phase 1, four rows (one weight float4) per step; the next step's
         // weights are loaded ahead
 #pragma unroll 1
@@ -299,47 +320,74 @@ __global__ __launch_bounds__(kPairBlock, K <= 12 ? 3 : 2) void k_sm_bwd(SmArgs a
                 const float wt = comp4(w4, rr);
                 const float *yi = yi0 + i * kp;
                 float d[K];
-                float acc = 0.0f;
+                float acc2 = 0.0f;
 #pragma unroll
                 for (int q = 0; q < K; ++q) {
                     d[q] = yi[q] - yj[q];
-                    acc = __builtin_fmaf(d[q], d[q], acc);
+                    acc2 = __builtin_fmaf(d[q], d[q], acc2);
                 }
-                const float r2 = acc * wt;
+                // r2 > 0 also excludes the masked pairs (1/d^2 < 0)
+                const float r2 = acc2 * wt;
                 const float rinv = __builtin_amdgcn_rsqf(r2);
                 const float rv = r2 * rinv;
-                const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(-rv, c2, Lc));
-                const float av = (wt > 0.0f && r2 > 0.0f) ? e * wt * rinv : 0.0f;
+                const float ex = __builtin_amdgcn_exp2f(__builtin_fmaf(-rv, c2, Lc));
+                const float av = r2 > 0.0f ? ex * wt * rinv : 0.0f;
 #pragma unroll
                 for (int q = 0; q < K; ++q) zc[q] = __builtin_fmaf(-av, d[q], zc[q]);
-                al[i * 65 + lane] = av;
+                al[i * kAStride + lane] = av;
+            }
+        }
+        float *zcol = a.Zc + h * (int64_t)(K * 64) + lane * K;
+#pragma unroll
+        for (int q = 0; q < K; ++q) zcol[q] = zc[q];
+        __builtin_amdgcn_wave_barrier();
+        // phase 2: A[16 mb + c16][4 tt + r4] from LDS, B = Y_J[4 tt + r4][c16]
+        double4_t accr0 = {0.0, 0.0, 0.0, 0.0}, accr1 = {0.0, 0.0, 0.0, 0.0};
+        double rs0 = 0.0, rs1 = 0.0;
+#pragma unroll 4
+        for (int tt = 0; tt < 16; ++tt) {
+            const int jc = 4 * tt + r4;
+            const float yv = yc0[jc * kp + qc];
+            const double bq = qin ? (double)yv : bpad;
+            const double a0 = (double)alr[4 * tt];
+            const double a1 = (double)alr[16 * kAStride + 4 * tt];
+            if constexpr (K == 16) {
+                rs0 += a0;
+                rs1 += a1;
+            }
+            accr0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bq, accr0, 0, 0, 0);
+            accr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bq, accr1, 0, 0, 0);
+        }
+        if constexpr (K == 16) {
+            rs0 += __shfl_xor(rs0, 16, kWave);
+            rs0 += __shfl_xor(rs0, 32, kWave);
+            rs1 += __shfl_xor(rs1, 16, kWave);
+            rs1 += __shfl_xor(rs1, 32, kWave);
+        }
+        float *zrow = a.Zr + h * (int64_t)(K * 32);
+        // lane holds (A Y_J)[16 mb + r4 + 4 v][c16]; row (r4 + 4 v)'s sum sits
+        // in the lanes with c16 = r4 + 4 v (K = 16), or in column 15 of the
+        // product, lane (r4, 15) (K < 16)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i0 = r4 + 4 * v, i1 = 16 + r4 + 4 * v;
+            double s0, s1;
+            if constexpr (K == 16) {
+                const int src = (lane & 48) | (r4 + 4 * v);
+                s0 = __shfl(rs0, src, kWave);
+                s1 = __shfl(rs1, src, kWave);
+            } else {
+                s0 = __shfl(accr0[v], (lane & 48) | 15, kWave);
+                s1 = __shfl(accr1[v], (lane & 48) | 15, kWave);
+            }
+            const double z0 = s0 * (double)yi0[i0 * kp + qc] - accr0[v];
+            const double z1 = s1 * (double)yi0[i1 * kp + qc] - accr1[v];
+            if (qin) {
+                zrow[i0 * K + c16] = (float)z0;
+                zrow[i1 * K + c16] = (float)z1;
             }
         }
         __builtin_amdgcn_wave_barrier();
-        // phase 2
-        float yo[K], zr[K];
-        const float *yown = yi0 + ri * kp;
-#pragma unroll
-        for (int q = 0; q < K; ++q) { yo[q] = yown[q]; zr[q] = 0.0f; }
-        const float *ycf = reinterpret_cast<const float *>(ycl) + hh * 32 * kp;
-        const float *arow = al + ri * 65 + hh * 32;
-#pragma unroll 2
-        for (int jj = 0; jj < 32; ++jj) {
-            const float av = arow[jj];
-            const float *yc = ycf + jj * kp;
-#pragma unroll
-            for (int q = 0; q < K; ++q) zr[q] = __builtin_fmaf(av, yo[q] - yc[q], zr[q]);
-        }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int q = 0; q < K; ++q) zr[q] += __shfl_xor(zr[q], 32, kWave);
-        float *zrow = a.Zr + h * (int64_t)(K * 32);
-        float *zcol = a.Zc + h * (int64_t)(K * 64);
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-            zcol[q * 64 + lane] = zc[q];
-            if (lane < 32) zrow[q * 32 + lane] = zr[q];
-        }
     }
 }
 
@@ -366,40 +414,40 @@ __global__ __launch_bounds__(kPairBlock) void k_sm_zred(SmArgs a, int64_t nb, in
     // two tiles per step, all their loads issued before the adds
     int64_t bj = b + wv;
     for (; bj + 4 < nb; bj += 8) {
-        const float *z0 = a.Zr + (2 * (trow0 + bj - b) + half) * (int64_t)(K * 32) + rr;
+        const float *z0 = a.Zr + (2 * (trow0 + bj - b) + half) * (int64_t)(K * 32) + rr * K;
         const float *z1 = z0 + 8 * (int64_t)(K * 32);   // tile bj + 4 of the same row
         float t0[K], t1[K];
 #pragma unroll
-        for (int q = 0; q < K; ++q) { t0[q] = z0[q * 32]; t1[q] = z1[q * 32]; }
+        for (int q = 0; q < K; ++q) { t0[q] = z0[q]; t1[q] = z1[q]; }
 #pragma unroll
         for (int q = 0; q < K; ++q) z[q] += (double)t0[q] + (double)t1[q];
     }
     for (; bj < nb; bj += 4) {
-        const float *zp = a.Zr + (2 * (trow0 + bj - b) + half) * (int64_t)(K * 32) + rr;
+        const float *zp = a.Zr + (2 * (trow0 + bj - b) + half) * (int64_t)(K * 32) + rr * K;
 #pragma unroll
-        for (int q = 0; q < K; ++q) z[q] += (double)zp[q * 32];
+        for (int q = 0; q < K; ++q) z[q] += (double)zp[q];
     }
     int64_t bi = wv;
     for (; bi + 4 <= b; bi += 8) {
         const int64_t t0 = bi * nb - bi * (bi - 1) / 2 + (b - bi);
         const int64_t bi1 = bi + 4;
         const int64_t t1 = bi1 * nb - bi1 * (bi1 - 1) / 2 + (b - bi1);
-        const float *z0 = a.Zc + 2 * t0 * (int64_t)(K * 64) + lane;
-        const float *z1 = a.Zc + 2 * t1 * (int64_t)(K * 64) + lane;
+        const float *z0 = a.Zc + 2 * t0 * (int64_t)(K * 64) + lane * K;
+        const float *z1 = a.Zc + 2 * t1 * (int64_t)(K * 64) + lane * K;
         float u0[K], u1[K], v0[K], v1[K];
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            u0[q] = z0[q * 64]; v0[q] = z0[K * 64 + q * 64];
-            u1[q] = z1[q * 64]; v1[q] = z1[K * 64 + q * 64];
+            u0[q] = z0[q]; v0[q] = z0[K * 64 + q];
+            u1[q] = z1[q]; v1[q] = z1[K * 64 + q];
         }
 #pragma unroll
         for (int q = 0; q < K; ++q) z[q] += ((double)u0[q] + (double)v0[q]) + ((double)u1[q] + (double)v1[q]);
     }
     for (; bi <= b; bi += 4) {
         const int64_t t = bi * nb - bi * (bi - 1) / 2 + (b - bi);
-        const float *zp = a.Zc + 2 * t * (int64_t)(K * 64) + lane;
+        const float *zp = a.Zc + 2 * t * (int64_t)(K * 64) + lane * K;
 #pragma unroll
-        for (int q = 0; q < K; ++q) z[q] += (double)zp[q * 64] + (double)zp[K * 64 + q * 64];
+        for (int q = 0; q < K; ++q) z[q] += (double)zp[q] + (double)zp[K * 64 + q];
     }
     const int64_t p = b * kTile + lane;
     if (a.nclose > 0 && p < N) {
@@ -425,23 +473,58 @@ __global__ __launch_bounds__(kPairBlock) void k_sm_zred(SmArgs a, int64_t nb, in
 }
 
 #ifndef SAP_KINST
-// G_c = sum_{p in chunk c} (x_p - mu) z_p^T, one output element (l, q) per
-// thread (element e = q n + l: consecutive threads read consecutive x).
+// G_c = sum_{p in chunk c} (x_p - mu) z_p^T (n x K, element e = q n + l) on
+// the matrix cores in FP64 (v_mfma_f64_16x16x4f64): output rows are 16
+// components l of x, the contraction runs over the chunk's points four at a
+// time.  Lane (c16, r4) feeds A = x[p][16 mb + c16] - mu and B = z[p][c16]
+// for p = p0 + 4 s + r4; wavefront w takes the component blocks mb = w,
+// w + 4, ...  Rows past the chunk and columns past n or K contribute 0
+// (selects, not multiplies, so no value of a masked element matters).
 template <typename TX>
 __global__ __launch_bounds__(256) void k_sm_grad(const TX *__restrict__ X, int64_t ldx, int64_t N,
                                                  int n, int K, const double *__restrict__ mu,
                                                  const double *__restrict__ Z, int64_t rows,
                                                  double *__restrict__ Gpart) {
-    const int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)n * K) return;
-    const int l = (int)(e % n), q = (int)(e / n);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c16 = lane & 15, r4 = lane >> 4;
     const int64_t p0 = (int64_t)blockIdx.x * rows;
     const int64_t p1 = p0 + rows < N ? p0 + rows : N;
-    const double ml = mu[l];
-    double acc = 0.0;
-    for (int64_t p = p0; p < p1; ++p)
-        acc = __builtin_fma((double)X[p * ldx + l] - ml, Z[p * K + q], acc);
-    Gpart[(int64_t)blockIdx.x * n * K + e] = acc;
+    const int64_t nsteps = (p1 - p0 + 3) / 4;
+    const int nmb = (n + 15) / 16;
+    const bool qin = c16 < K;
+    const int qc = qin ? c16 : K - 1;
+    double *out = Gpart + (int64_t)blockIdx.x * n * K;
+    for (int mb = wv; mb < nmb; mb += 4) {
+        const int l = 16 * mb + c16;
+        const bool lin = l < n;
+        const int lc = lin ? l : n - 1;
+        const double ml = mu[lc];
+        double4_t acc = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t s0 = 0; s0 < nsteps; s0 += 4) {
+            double xa[4], zb[4];
+            bool pin[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t p = p0 + 4 * (s0 + u) + r4;
+                pin[u] = p < p1;
+                const int64_t pc = pin[u] ? p : p0;
+                xa[u] = (double)X[pc * ldx + lc];
+                zb[u] = Z[pc * K + qc];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double av = (pin[u] && lin) ? xa[u] - ml : 0.0;
+                const double bv = (pin[u] && qin) ? zb[u] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+        }
+        // lane holds G[16 mb + r4 + 4 v][c16]
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int lo = 16 * mb + r4 + 4 * v;
+            if (lo < n && qin) out[(int64_t)c16 * n + lo] = acc[v];
+        }
+    }
 }
 
 // dP (n x k row-major FP32) = dL/dloss * sum over the chunks: one block per

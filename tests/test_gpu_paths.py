@@ -8,6 +8,8 @@
     reported uncertified -- it is then still an exact FP64 value of a real
     pair, and a certified result always equals the oracle's;
   * work items whose pairs are all masked (an empty rescoring window);
+  * short pairs bounded from the unrounded FP64 projection, evaluated
+    exactly only where one of their block's two smallest values may lie;
   * the runner-up field against the oracle's second-smallest value;
   * the soft-min backward refusing a P other than its forward's.
 """
@@ -240,6 +242,61 @@ def test_work_items_of_only_short_secants(form):
     assert (res["i"], res["j"]) == (ref["i"], ref["j"]) or ref["r_second"] - ref["r_min"] < NEAR_TIE
     assert abs(res["min_norm"] - ref["r_min"]) <= min_tol(ref["r_min"], 8, 3)
     assert ctx.info()["n_dropped"] == ref["n_dropped"] >= 280 * 279 // 2
+    ctx.close()
+
+
+# ------------------------------------------------------------------ short pairs from the FP64 Y
+
+@pytest.mark.parametrize("name,N,k", [("trig64", 300, 6), ("blob", 260, 4), ("hyper", 330, 10)])
+def test_every_pair_short_lockstep(name, N, k):
+    """Every pair on the short-pair list (close_d above every distance): with
+    the FP64 GEMM each pair is bounded from the unrounded Y and few are
+    evaluated exactly; the results are the oracle's over a lockstep run, and
+    the same exact values as with every short pair evaluated exactly (FP32
+    GEMM, no FP64 Y)."""
+    w = sap_inputs.make(name, N=N, k=k)
+    p = N * (N - 1) // 2
+    kw = dict(form="fused", close_d=1e30, close_cap=p)
+    a = _ctx(w.X, w.P0, gemm="f64", **kw)
+    b = _ctx(w.X, w.P0, gemm="f32", **kw)
+    assert a.info()["n_close"] == p
+    n_exact = []
+    for it in range(8):
+        P = a.get_P().cpu().numpy()
+        ra = a.step(sync=True)
+        rb = b.step(sync=True)
+        _check_certified(w.X, P, ra, f"{name} it{it}")
+        assert (ra["i"], ra["j"], ra["min_norm"]) == (rb["i"], rb["j"], rb["min_norm"]), (it, ra, rb)
+        assert ra["runner_up"] == rb["runner_up"] and ra["runner_up_exact"] == rb["runner_up_exact"] == 1
+        assert np.array_equal(a.get_P().cpu().numpy(), b.get_P().cpu().numpy())
+        n_exact.append(ra["n_rescored"])
+    print(f"[short64] {name}/N{N}/k{k}: {p} short pairs, exactly evaluated per iteration "
+          f"{np.mean(n_exact):.0f} (FP32 GEMM: all {p})", flush=True)
+    assert max(n_exact) < p // 10
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_short_pair_ties_and_runner_up(dtype):
+    """The planted five-way exact tie of the runner-up test with every pair
+    short: all five tied pairs are exactly evaluated, the smallest pair
+    index wins and the runner-up is exact."""
+    rng = np.random.default_rng(11)
+    N, n, k = 300, 8, 2
+    X = rng.integers(-50, 51, size=(N, n)).astype(np.float64)
+    X[:, 0] = 4.0 * rng.permutation(N)
+    delta = np.array([1, 0, 300, 400, 200, -100, 250, 350], dtype=np.float64)
+    for a_, b_ in ((250, 260), (40, 290), (7, 8), (120, 5), (299, 150)):
+        X[b_] = X[a_] + delta
+    X = X.astype(dtype)
+    P = np.zeros((n, k))
+    P[0, 0] = P[1, 1] = 1.0
+    ctx = _ctx(X, P, form="fused", close_d=1e30, close_cap=N * (N - 1) // 2)
+    res = ctx.min_secant()
+    ref = _check_certified(X, P, res, "short ties")
+    assert (res["i"], res["j"]) == (ref["i"], ref["j"])
+    assert res["runner_up_exact"] == 1 and res["runner_up"] == res["min_norm"] == ref["r_second"]
     ctx.close()
 
 

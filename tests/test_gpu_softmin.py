@@ -76,6 +76,15 @@ def test_softmin_matches_oracle(name, N, k, tau):
     _compare(w.X, w.P0, tau, f"{name}/N{N}/k{k}")
 
 
+@pytest.mark.parametrize("k", list(range(1, 17)))
+def test_softmin_every_k(k):
+    """Every compiled projection width K = 1..16 (each its own kernel
+    instance, with its own LDS row length and matrix-core padding) on a
+    multi-tile torus sample."""
+    w = sap_inputs.make("torus", N=200, k=k)
+    _compare(w.X, w.P0, 0.01, f"torus/N200/k{k}")
+
+
 @pytest.mark.parametrize("N", [1, 63, 64, 65, 130])
 def test_softmin_ragged_sizes(N):
     """One point short of, at, and past a 64-point tile; N = 1 + 1 pair."""
