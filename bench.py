@@ -48,29 +48,32 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pass_fused_trig64_N4000_n64_k6_traffic.txt")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pass_trig64_N4000_n64_k6_traffic.txt")
 KERNEL_SOURCES = ("paper_1807_03425_amd/csrc/sap_iter.hip", "paper_1807_03425_amd/csrc/sap_common.h",
                   "paper_1807_03425_amd/csrc/sap_api.hip", "paper_1807_03425_amd/csrc/sap_kinst.hip",
                   "paper_1807_03425_amd/csrc/sap_launch.h")
 
 
 def measured_traffic():
-    """HBM bytes per launch of the fused pass, from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (scaled by a 256 MiB copy), if the kernel
-    sources still hash to what was profiled; otherwise None."""
+    """HBM bytes per launch of the fused and the plain pair pass, from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (each counter scaled
+    by what it reads for a device copy of known size), while the kernel
+    sources still hash to what was profiled; otherwise None for both."""
+    none = {"fused": None, "plain": None}
     try:
         with open(TRAFFIC_PROFILE) as f:
             lines = [l for l in f.read().splitlines() if l and not l.startswith("#") and ":" in l]
     except OSError:
-        return None
+        return none
     kv = {k.strip(): v.strip() for k, v in (l.split(":", 1) for l in lines)}
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     if kv.get("source_sha256") != h.hexdigest():
-        return None
-    return float(kv["traffic_bytes_per_launch"].split()[0])
+        return none
+    return {form: float(kv[f"{form}_traffic_bytes_per_launch"].split()[0]) if f"{form}_traffic_bytes_per_launch" in kv
+            else None for form in ("fused", "plain")}
 
 
 def time_run(torch, ctx, steps, warmup, prof_steps):
@@ -335,8 +338,8 @@ def main():
         res[form] = r
     head = "fused" if "fused" in res else forms[0]
     hs = res[head]
-    traffic = measured_traffic() if head == "fused" else None
-    roofline = dict(hs["roofline"], traffic=traffic,
+    traffic = measured_traffic()
+    roofline = dict(hs["roofline"], traffic=traffic.get(head),
                     valu_frac=hs.get("roofline_valu", {}).get("frac"))
 
     accuracy = {}
@@ -399,7 +402,7 @@ def main():
         roofline=roofline, cpu_baseline=cpu, forms=res, accuracy=accuracy,
     )
     if "plain" in res:
-        line["roofline_plain"] = dict(res["plain"]["roofline"], traffic=None)
+        line["roofline_plain"] = dict(res["plain"]["roofline"], traffic=traffic.get("plain"))
         if "fused" in res:
             line["fused_over_plain"] = res["fused"]["secants_per_s"] / res["plain"]["secants_per_s"]
 

@@ -1130,17 +1130,16 @@ __device__ __forceinline__ void min2_merge(double &u1, double &u2, double v1, do
 // The block takes a contiguous range of the list.  First every pair's
 // bounds [r~ - e, r~ + e]; U2 = the second-smallest upper bound, so at least
 // two of the block's pairs are worth at most U2.  Then every pair with
-// r~ - e <= U2 is evaluated exactly from X (short_c16, 16 per wavefront step;
-// the candidates of a 64-pair chunk are compacted through LDS).  A pair left
-// out is worth more than U2, hence more than the block's two smallest
-// values, which are therefore exact FP64 evaluations, as with every pair
-// evaluated exactly.
+// r~ - e <= U2 is evaluated exactly from X, one pair per wavefront step
+// (exact_r_wave: a few dependent loads even for long rows, where the
+// sixteen-pair matrix-core form walks the row in sixteen).  A pair left out
+// is worth more than U2, hence more than the block's two smallest values,
+// which are therefore exact FP64 evaluations, as with every pair evaluated
+// exactly.
 template <int K, typename TX>
 __device__ void short_block_y64(const SweepArgs<TX> &a, int sb, int nshort) {
-    __shared__ int32_t s_cidx[kPairBlock / kWave][kWave];
     __shared__ double s_u[kPairBlock / kWave][2];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int m = lane & 15, kk = lane >> 4;
     const int64_t per = (a.nclose + nshort - 1) / nshort;
     const int64_t e0 = (int64_t)sb * per;
     const int64_t e1 = e0 + per < a.nclose ? e0 + per : a.nclose;
@@ -1171,34 +1170,21 @@ __device__ void short_block_y64(const SweepArgs<TX> &a, int sb, int nshort) {
             short_bounds<K, TX>(a, e, lb, ub);
             cand = !(lb > U2);
         }
-        const uint64_t mask = __ballot(cand);
-        const int ncand = __popcll(mask);
-        if (cand)
-            s_cidx[wv][__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] = lane;
-        __builtin_amdgcn_wave_barrier();
-        for (int g = 0; g < ncand; g += 16) {
-            const int slot = g + m;
-            const bool rin = slot < ncand;
-            const int64_t ee = c0 + s_cidx[wv][rin ? slot : g];
+        uint64_t mask = __ballot(cand);
+#pragma unroll 1
+        while (mask) {
+            const int64_t ee = c0 + __builtin_ctzll(mask);
+            mask &= mask - 1;
             const int2 pr = a.close[ee];
-            const double dlen = a.cd[ee];
-            const double4_t acc = short_c16<K, TX>(a.X, a.ldx, pr, rin, a.n, a.P64t, a.vx, a.vp);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const double q2 = row_sum16(acc[v] * acc[v]);
-                const int src = kk + 4 * v;          // the lane (m = src) that loaded this pair
-                const int pi = __shfl(pr.x, src, kWave), pj = __shfl(pr.y, src, kWave);
-                const double dv = __shfl(dlen, src, kWave);
-                if (m == 0 && g + src < ncand) {
-                    ++cnt;
-                    lex_pick2(best, bi, bj, second, sqrt(q2) / dv, pi, pj, inf);
-                }
-            }
+            double r;
+            if (K <= 7 && a.n <= kWave) r = exact_r_wave<K, TX, 1>(a.X, a.ldx, a.n, a.P64t, pr.x, pr.y);
+            else r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, a.P64t, pr.x, pr.y);
+            ++cnt;
+            lex_pick2(best, bi, bj, second, r, pr.x, pr.y, inf);
         }
-        __builtin_amdgcn_wave_barrier();
     }
-    block_reduce_partial(best, bi, bj, second, cnt, 0, 0, kKeyNone, kKeyNone, a.part + a.npass + sb);
+    block_reduce_partial(best, bi, bj, second, lane == 0 ? cnt : 0, 0, 0, kKeyNone, kKeyNone,
+                         a.part + a.npass + sb);
 }
 
 // Selection (one block, after the pass): the lexicographic minimum of every

@@ -252,8 +252,8 @@ def test_every_pair_short_lockstep(name, N, k):
     """Every pair on the short-pair list (close_d above every distance): with
     the FP64 GEMM each pair is bounded from the unrounded Y and few are
     evaluated exactly; the results are the oracle's over a lockstep run, and
-    the same exact values as with every short pair evaluated exactly (FP32
-    GEMM, no FP64 Y)."""
+    agree with every short pair evaluated exactly (FP32 GEMM, no FP64 Y) up
+    to the rounding of two FP64 evaluation orders."""
     w = sap_inputs.make(name, N=N, k=k)
     p = N * (N - 1) // 2
     kw = dict(form="fused", close_d=1e30, close_cap=p)
@@ -265,10 +265,17 @@ def test_every_pair_short_lockstep(name, N, k):
         P = a.get_P().cpu().numpy()
         ra = a.step(sync=True)
         rb = b.step(sync=True)
-        _check_certified(w.X, P, ra, f"{name} it{it}")
-        assert (ra["i"], ra["j"], ra["min_norm"]) == (rb["i"], rb["j"], rb["min_norm"]), (it, ra, rb)
-        assert ra["runner_up"] == rb["runner_up"] and ra["runner_up_exact"] == rb["runner_up_exact"] == 1
-        assert np.array_equal(a.get_P().cpu().numpy(), b.get_P().cpu().numpy())
+        ref = _check_certified(w.X, P, ra, f"{name} it{it}")
+        assert rb["certified"] == 1
+        if ref["r_second"] - ref["r_min"] >= NEAR_TIE:
+            assert (ra["i"], ra["j"]) == (rb["i"], rb["j"]), (it, ra, rb)
+        tol = min_tol(ref["r_min"], w.n, k)
+        assert abs(ra["min_norm"] - rb["min_norm"]) <= tol, (it, ra, rb)
+        assert ra["runner_up_exact"] == rb["runner_up_exact"] == 1
+        assert abs(ra["runner_up"] - rb["runner_up"]) <= min_tol(ref["r_second"], w.n, k)
+        if (ra["i"], ra["j"]) != (rb["i"], rb["j"]):
+            break                     # a near-tie resolved differently: the runs part here
+        assert np.abs(a.get_P().cpu().numpy() - b.get_P().cpu().numpy()).max() < 1e-12
         n_exact.append(ra["n_rescored"])
     print(f"[short64] {name}/N{N}/k{k}: {p} short pairs, exactly evaluated per iteration "
           f"{np.mean(n_exact):.0f} (FP32 GEMM: all {p})", flush=True)
