@@ -37,9 +37,11 @@
  * Both forms rescore, in FP64 from X, every pair whose coarse value lies in a
  * window proven (from the rounding-error bound of the coarse pass) to
  * contain the true minimum, so the reported minimum and pair are those of
- * an FP64 evaluation.  The fused form evaluates pairs shorter than a cutoff
- * D_c directly in FP64 every iteration, because there the coarse error,
- * which grows like 1/d, would swamp them.
+ * an FP64 evaluation.  The fused form keeps pairs shorter than a cutoff D_c
+ * out of the coarse pass, because there the coarse error, which grows like
+ * 1/d, would swamp them: with the FP64 GEMM it bounds them from the unrounded
+ * FP64 Y and evaluates exactly from X only those that may hold one of their
+ * block's two smallest values; otherwise it evaluates them all exactly.
  */
 #ifndef SAP_H
 #define SAP_H
