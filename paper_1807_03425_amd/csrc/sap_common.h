@@ -111,12 +111,10 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
     return v;
 }
 
-// lexicographic (r, i, j) minimum
+// lexicographic (r, i, j) order (no branches; false whenever r or r2 is NaN)
 __device__ __forceinline__ bool lex_less(double r, int32_t i, int32_t j, double r2,
                                          int32_t i2, int32_t j2) {
-    if (r != r2) return r < r2;
-    if (i != i2) return i < i2;
-    return j < j2;
+    return (r < r2) | ((r == r2) & ((i < i2) | ((i == i2) & (j < j2))));
 }
 
 __device__ __forceinline__ void wave_min_lex(double &r, int32_t &i, int32_t &j) {

@@ -32,11 +32,14 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ wavefront sums
 
-// DPP lane permutation of a double (two 32-bit moves).
+// DPP lane permutation of a double (two 32-bit moves).  Every control used
+// here (quad permutations, half-row and row mirrors, row rotations) reads a
+// valid lane for every lane, so the moves take no "old" operand: that would
+// cost a register initialisation per move.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 
@@ -510,24 +513,27 @@ __device__ __forceinline__ int bound_broken(double r, double r2c, double e_abs, 
 
 template <int CTRL>
 __device__ __forceinline__ int dpp_i32(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
 }
 
 // (r, i, j) <- the lexicographic minimum of (r, i, j) and (r', i', j'), and r2
 // <- the second-smallest value of the two top-2 sets: the smaller of the two
 // second values and the first value of the tuple that lost.  The same pair
 // on both sides (the lanes of a wavefront that rescored cooperatively hold
-// identical results) is one element: only the second values merge.
+// identical results; a clamped duplicate load) is one element: only the
+// second values merge.  Selects only: these merges form long dependent
+// chains in single-wavefront code, where exec-mask branches cost far more
+// than the few extra selects.
 __device__ __forceinline__ void lex_pick2(double &r, int32_t &i, int32_t &j, double &r2, double rb, int32_t ib,
                                           int32_t jb, double r2b) {
-    if (ib == i && jb == j) {
-        r2 = fmin(r2, r2b);
-    } else if (lex_less(rb, ib, jb, r, i, j)) {
-        r2 = fmin(fmin(r2, r2b), r);
-        r = rb; i = ib; j = jb;
-    } else {
-        r2 = fmin(fmin(r2, r2b), rb);
-    }
+    const bool same = (ib == i) & (jb == j);
+    const bool less = !same & lex_less(rb, ib, jb, r, i, j);
+    const double lost = less ? r : rb;   // the first value of the tuple that lost
+    const double m2 = fmin(r2, r2b);
+    r2 = same ? m2 : fmin(m2, lost);
+    r = less ? rb : r;
+    i = less ? ib : i;
+    j = less ? jb : j;
 }
 
 template <int CTRL>
@@ -1209,23 +1215,21 @@ __device__ int2 select_min(const SweepArgs<TX> &a, int nparts, bool record) {
     uint32_t kmin = kKeyNone, limit = kKeyNone;
 #pragma unroll 1
     for (int base = 0; base < nparts; base += 8 * kPairBlock) {
+        // unconditional loads (clamped index, nparts >= 1): a guarded load
+        // would wait alone, and so would one whose registers are overwritten
+        // past the end.  A clamped duplicate of the last partial is the same
+        // element to the top-2 merge and the minima; only its counts are
+        // masked.
         Partial p[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            // unconditional loads (clamped index, nparts >= 1), then the
-            // neutral element past the end: a guarded load would wait alone
-            const int ix = base + u * kPairBlock + (int)threadIdx.x;
-            p[u] = a.part[min(ix, nparts - 1)];
-            if (ix >= nparts)
-                p[u] = Partial{__builtin_huge_val(), __builtin_huge_val(), 0x7fffffff, 0x7fffffff, 0, 0, 0,
-                               kKeyNone, kKeyNone, 0};
-        }
+        for (int u = 0; u < 8; ++u) p[u] = a.part[min(base + u * kPairBlock + (int)threadIdx.x, nparts - 1)];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
+            const bool in = base + u * kPairBlock + (int)threadIdx.x < nparts;
             lex_pick2(best, bi, bj, second, p[u].r, p[u].i, p[u].j, p[u].r2);
-            nres += p[u].n_rescored;
-            nunits += p[u].n_units;
-            nviol += p[u].n_viol;
+            nres += in ? p[u].n_rescored : 0;
+            nunits += in ? p[u].n_units : 0;
+            nviol += in ? p[u].n_viol : 0;
             kmin = min(kmin, p[u].kmin);
             limit = min(limit, p[u].limit);
         }
