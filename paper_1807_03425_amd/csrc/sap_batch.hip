@@ -469,7 +469,7 @@ __device__ void batch_problem(const BatchArgs &a, int b, double *sm, BatchLds &L
             }
             wb.nviol += cl.lost;
             block_reduce_partial(wb.r, wb.i, wb.j, wb.r2, lane == 0 ? wb.nwin : 0, lane == 0 ? wb.nunits : 0,
-                                 lane == 0 ? wb.nviol : 0, kmin, cl.limit, &s_fin);
+                                 lane == 0 ? wb.nviol : 0, kmin, cl.limit, &s_fin, true);
         }
         const Partial f = s_fin;
         const bool found = f.r < __builtin_huge_val();

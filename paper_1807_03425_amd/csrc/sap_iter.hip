@@ -152,17 +152,33 @@ __device__ __forceinline__ void load16_raw(const T *__restrict__ p, bool vec, T 
 // l0 + 16 kk + s, so each lane reads 16 consecutive components of its row
 // (and of P's column): 16-byte loads when vx (X rows 16-byte aligned) and vp
 // (n even).  Every operand load of a chunk is issued before its 16 MFMAs.
-// The lane's operands of gemm_block's first chunk (n >= 64): 16 values of
-// its X row and the matching 16 column means.
+// The lane's operands of gemm_block's first chunk (used when n >= 64 and X
+// rows take 16-byte loads): 16 values of its X row (in X's type: converted
+// at use, so that nothing waits for these loads where they are issued) and
+// the matching 16 column means.  The loads are issued whether or not they
+// are used (from `spare`, any 16-byte aligned 512 bytes of device memory,
+// when not): with no branch around them, the wait for loads issued earlier
+// stays exact.
 template <typename TX>
 __device__ __forceinline__ void gemm_first_x(const TX *__restrict__ X, int64_t ldx, int64_t N, int64_t Npad,
-                                             bool vx, const double *__restrict__ mu, double (&xa)[16],
-                                             double (&ma)[16]) {
+                                             bool use, const void *spare, const double *__restrict__ mu,
+                                             TX (&xa)[16], double (&ma)[16]) {
     const int lane = threadIdx.x & 63;
     const int64_t row0 = min(((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16, Npad - 16);
     const int64_t row = row0 + (lane & 15);
-    load16(X + (row < N ? row : N - 1) * ldx + 16 * (lane >> 4), vx, xa);
-    load16(mu + 16 * (lane >> 4), true, ma);
+    const TX *xp = use ? X + (row < N ? row : N - 1) * ldx + 16 * (lane >> 4) : static_cast<const TX *>(spare);
+    const double *mp = use ? mu + 16 * (lane >> 4) : static_cast<const double *>(spare);
+    load16_raw(xp, true, xa);
+    load16_raw(mp, true, ma);
+}
+template <typename TX>
+__device__ __forceinline__ void gemm_first_x_scalar(const TX *__restrict__ X, int64_t ldx, int64_t N, int64_t Npad,
+                                                    const double *__restrict__ mu, TX (&xa)[16], double (&ma)[16]) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row0 = min(((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16, Npad - 16);
+    const int64_t row = row0 + (lane & 15);
+    load16_raw(X + (row < N ? row : N - 1) * ldx + 16 * (lane >> 4), false, xa);
+    load16_raw(mu + 16 * (lane >> 4), true, ma);
 }
 
 typedef float float4_mfma __attribute__((ext_vector_type(4)));
@@ -183,7 +199,7 @@ template <typename TX>
 __device__ __forceinline__ void gemm_block_lowp(const TX *__restrict__ X, int64_t ldx, int64_t N, int n, int k,
                                                 const double *__restrict__ mu, const double *__restrict__ P64t,
                                                 float *__restrict__ Y, int kp, int64_t row0, bool vx, bool vp,
-                                                const double (&x0)[16], const double (&m0)[16], bool use_x0,
+                                                const TX (&x0)[16], const double (&m0)[16], bool use_x0,
                                                 int gemm) {
     const int lane = threadIdx.x & 63;
     const int m = lane & 15, kk = lane >> 4;
@@ -199,7 +215,12 @@ __device__ __forceinline__ void gemm_block_lowp(const TX *__restrict__ X, int64_
         const int lb = l0 + 16 * kk;
         if (use_x0 && l0 == 0) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) { xa[u] = x0[u]; ma[u] = m0[u]; }
+            for (int u = 0; u < 16; ++u) {
+                TX t = x0[u];
+                asm volatile("" : "+v"(t));   // converted here, as in gemm_block
+                xa[u] = (double)t;
+                ma[u] = m0[u];
+            }
         } else {
             load16(xr + lb, vx, xa);
             load16(mu + lb, true, ma);
@@ -267,7 +288,7 @@ template <typename TX>
 __device__ __forceinline__ void gemm_block(const TX *__restrict__ X, int64_t ldx, int64_t N, int n, int k,
                            const double *__restrict__ mu, const double *__restrict__ P64t,
                            float *__restrict__ Y, double *__restrict__ Y64, int kp, int64_t Npad, bool vx,
-                           bool vp, const double (&x0)[16], const double (&m0)[16], bool use_x0, int gemm) {
+                           bool vp, const TX (&x0)[16], const double (&m0)[16], bool use_x0, int gemm) {
     const int lane = threadIdx.x & 63;
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
     if (row0 >= Npad) return;
@@ -292,7 +313,14 @@ __device__ __forceinline__ void gemm_block(const TX *__restrict__ X, int64_t ldx
         double xa[16], ma[16], pb[16];
         if (use_x0) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) { xa[u] = x0[u]; ma[u] = m0[u]; }
+            for (int u = 0; u < 16; ++u) {
+                // converted here, not where the prefetch was issued (the empty
+                // asm pins the conversion after this point)
+                TX t = x0[u];
+                asm volatile("" : "+v"(t));
+                xa[u] = (double)t;
+                ma[u] = m0[u];
+            }
         } else {
             load16(xr + 16 * kk, vx, xa);
             load16(mu + 16 * kk, true, ma);
@@ -600,10 +628,14 @@ __device__ __forceinline__ uint32_t wave_min_u32_fast(uint32_t v) {
 }
 
 // Block-wide reduction of a per-thread top-2 (r, i, j; r2), counters, the
-// coarse minimum and the candidate-key limit into *out (written by thread 0).
-// All 256 threads must call it.
-__device__ void block_reduce_partial(double r, int32_t i, int32_t j, double r2, int32_t nres, int32_t ntl,
-                                     int32_t nviol, uint32_t kmin, uint32_t limit, Partial *out) {
+// coarse minimum and the candidate-key limit, returned in every thread (and
+// written to *out by thread 0 when out is non-null).  Every lane merges the
+// four wavefront results in the same order, so the whole block holds the
+// same value with one barrier.  All 256 threads must call it; sync_after
+// adds the barrier a later call needs before it may reuse the staging slots.
+__device__ Partial block_reduce_partial(double r, int32_t i, int32_t j, double r2, int32_t nres, int32_t ntl,
+                                        int32_t nviol, uint32_t kmin, uint32_t limit, Partial *out,
+                                        bool sync_after) {
     __shared__ Partial sb[kPairBlock / kWave];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     wave_min_lex2_fast(r, i, j, r2);
@@ -614,19 +646,20 @@ __device__ void block_reduce_partial(double r, int32_t i, int32_t j, double r2, 
     limit = wave_min_u32_fast(limit);
     if (lane == 0) sb[wv] = Partial{r, r2, i, j, nres, ntl, nviol, kmin, limit, 0};
     __syncthreads();
-    if (threadIdx.x == 0) {
-        Partial b = sb[0];
-        for (int w = 1; w < kPairBlock / kWave; ++w) {
-            lex_pick2(b.r, b.i, b.j, b.r2, sb[w].r, sb[w].i, sb[w].j, sb[w].r2);
-            b.n_rescored += sb[w].n_rescored;
-            b.n_units += sb[w].n_units;
-            b.n_viol += sb[w].n_viol;
-            b.kmin = min(b.kmin, sb[w].kmin);
-            b.limit = min(b.limit, sb[w].limit);
-        }
-        *out = b;
+    Partial b = sb[0];
+#pragma unroll
+    for (int w = 1; w < kPairBlock / kWave; ++w) {
+        const Partial o = sb[w];
+        lex_pick2(b.r, b.i, b.j, b.r2, o.r, o.i, o.j, o.r2);
+        b.n_rescored += o.n_rescored;
+        b.n_units += o.n_units;
+        b.n_viol += o.n_viol;
+        b.kmin = min(b.kmin, o.kmin);
+        b.limit = min(b.limit, o.limit);
     }
-    __syncthreads();
+    if (out && threadIdx.x == 0) *out = b;
+    if (sync_after) __syncthreads();
+    return b;
 }
 
 // ------------------------------------------------------------------ sweep
@@ -882,7 +915,7 @@ __device__ __forceinline__ void finish_pass_block(const SweepArgs<TX> &a, const 
     wb.nviol += cl.lost;   // dropped candidates: the result is not certified
     const int lane = threadIdx.x & 63;
     block_reduce_partial(wb.r, wb.i, wb.j, wb.r2, lane == 0 ? wb.nwin : 0, lane == 0 ? wb.nunits : 0,
-                         lane == 0 ? wb.nviol : 0, kmin, cl.limit, out);
+                         lane == 0 ? wb.nviol : 0, kmin, cl.limit, out, false);
 }
 
 // Fused pass block pb.  Wavefront w = 4 pb + slot takes work items
@@ -1098,7 +1131,7 @@ __device__ void short_block(const SweepArgs<TX> &a, int sb, int nshort) {
             }
         }
     }
-    block_reduce_partial(best, bi, bj, second, cnt, 0, 0, kKeyNone, kKeyNone, a.part + a.npass + sb);
+    block_reduce_partial(best, bi, bj, second, cnt, 0, 0, kKeyNone, kKeyNone, a.part + a.npass + sb, false);
 }
 
 // Bounds of one short pair's value from the unrounded projection Y64:
@@ -1190,15 +1223,26 @@ __device__ void short_block_y64(const SweepArgs<TX> &a, int sb, int nshort) {
         }
     }
     block_reduce_partial(best, bi, bj, second, lane == 0 ? cnt : 0, 0, 0, kKeyNone, kKeyNone,
-                         a.part + a.npass + sb);
+                         a.part + a.npass + sb, false);
+}
+
+// One step of the selection's loads: partials base + u * 256 + thread,
+// u = 0..7, unconditional (clamped index, nparts >= 1): a guarded load would
+// wait alone, and so would one whose registers are overwritten past the end.
+template <typename TX>
+__device__ __forceinline__ void select_load(const SweepArgs<TX> &a, int nparts, int base, Partial (&p)[8]) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) p[u] = a.part[min(base + u * kPairBlock + (int)threadIdx.x, nparts - 1)];
 }
 
 // Selection (one block, after the pass): the lexicographic minimum of every
 // pass block's and short-pair block's FP64 result, the record, and the
 // coarse minimum with its window (reported).  Eight partials per thread are
 // loaded per step, all before any is used (each step is a round trip to
-// memory written by other dies' caches).  Returns the winning pair in
-// every thread (i < 0 if there is none).
+// memory written by other dies' caches).  The caller issues the first
+// step's loads (select_load, base 0) and passes them in p, so that loads it
+// issues next queue behind them.  Returns the winning pair in every thread
+// (i < 0 if there is none).
 //
 // Certified: no rescored pair broke the coarse bound, no candidate was lost,
 // and every block's candidate-key limit lies at or above the window of the
@@ -1209,20 +1253,13 @@ __device__ void short_block_y64(const SweepArgs<TX> &a, int sb, int nshort) {
 // lower bound of the true runner-up, exact when the evaluated value is the
 // smaller.
 template <int K, typename TX, bool FUSED>
-__device__ int2 select_min(const SweepArgs<TX> &a, int nparts, bool record) {
+__device__ int2 select_min(const SweepArgs<TX> &a, int nparts, bool record, Partial (&p)[8]) {
     double best = __builtin_huge_val(), second = __builtin_huge_val();
     int32_t bi = 0x7fffffff, bj = 0x7fffffff, nres = 0, nunits = 0, nviol = 0;
     uint32_t kmin = kKeyNone, limit = kKeyNone;
-#pragma unroll 1
-    for (int base = 0; base < nparts; base += 8 * kPairBlock) {
-        // unconditional loads (clamped index, nparts >= 1): a guarded load
-        // would wait alone, and so would one whose registers are overwritten
-        // past the end.  A clamped duplicate of the last partial is the same
-        // element to the top-2 merge and the minima; only its counts are
-        // masked.
-        Partial p[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) p[u] = a.part[min(base + u * kPairBlock + (int)threadIdx.x, nparts - 1)];
+    // a clamped duplicate of the last partial (select_load) is the same
+    // element to the top-2 merge and the minima; only its counts are masked
+    auto merge_step = [&](int base) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const bool in = base + u * kPairBlock + (int)threadIdx.x < nparts;
@@ -1233,11 +1270,15 @@ __device__ int2 select_min(const SweepArgs<TX> &a, int nparts, bool record) {
             kmin = min(kmin, p[u].kmin);
             limit = min(limit, p[u].limit);
         }
+    };
+    merge_step(0);
+#pragma unroll 1
+    for (int base = 8 * kPairBlock; base < nparts; base += 8 * kPairBlock) {
+        select_load(a, nparts, base, p);
+        merge_step(base);
     }
-    __shared__ Partial s_fin;
-    block_reduce_partial(best, bi, bj, second, nres, nunits, nviol, kmin, limit, &s_fin);
+    const Partial f = block_reduce_partial(best, bi, bj, second, nres, nunits, nviol, kmin, limit, nullptr, false);
     if (record && threadIdx.x == 0) {
-        const Partial f = s_fin;
         double coarse, tr;
         (void)window_key(f.kmin, a.e_abs, a.e_rel, &coarse, &tr);
         const bool found = f.r < __builtin_huge_val();
@@ -1272,8 +1313,6 @@ __device__ int2 select_min(const SweepArgs<TX> &a, int nparts, bool record) {
         if (a.tr_cert) a.tr_cert[a.it] = cert;
         *a.gmin_out = f.kmin;
     }
-    __syncthreads();
-    const Partial f = s_fin;
     return f.r < __builtin_huge_val() ? make_int2(f.i, f.j) : make_int2(-1, -1);
 }
 
@@ -1302,8 +1341,9 @@ __global__ __launch_bounds__(kPairBlock, (FUSED || sizeof(TX) == 4 || K <= 12) ?
 template <int K, typename TX>
 __global__ __launch_bounds__(kPairBlock) void k_prep(SweepArgs<TX> a, const double *__restrict__ mu,
                                                      float *__restrict__ Y, int64_t Npad) {
+    const TX nx[16] = {};
     const double none[16] = {};
-    gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, a.P64t, Y, a.Y64, a.kp, Npad, a.vx, a.vp, none, none, false,
+    gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, a.P64t, Y, a.Y64, a.kp, Npad, a.vx, a.vp, nx, none, false,
                    a.gemm);
 }
 
@@ -1671,7 +1711,9 @@ __global__ __launch_bounds__(kPairBlock) void k_select(SweepArgs<TX> a, int nsho
     // P into LDS now, so that its loads overlap the selection (the block
     // barriers inside select_min order these writes before the update)
     if (do_step) stage_P(a.P64t, K * a.n, sm_dyn);
-    const int2 ij = select_min<K, TX, FUSED>(a, a.npass + nshort, true);
+    Partial p[8];
+    select_load(a, a.npass + nshort, 0, p);
+    const int2 ij = select_min<K, TX, FUSED>(a, a.npass + nshort, true, p);
     if (do_step && ij.x >= 0) {
         // one wavefront with the vectors in registers when every vector
         // fits one 64-lane slice and K is small, the whole block over LDS
@@ -1700,23 +1742,23 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
                                                         float *__restrict__ Y, int64_t Npad) {
     extern __shared__ __align__(16) double sm_sp[];
     const bool lead = blockIdx.x == 0;
-    // small P: its loads are issued first and land in registers while the
-    // selection's loads are in flight (one wait covers both); it goes to
-    // LDS after the selection, before the barrier the update starts behind
+    // small P (into registers, then to LDS after the selection, before the
+    // barrier the update starts behind), the GEMM's first chunk of X and the
+    // means are loaded right behind the selection's first loads: the
+    // selection waits for its own loads only, and these land meanwhile
     const int kn = K * a.n;
     const bool small = kn <= 8 * kPairBlock;
-    // the GEMM's first chunk of X and of the means are loaded now too, out of
-    // the critical path
-    double x0[16], m0[16];
-    if (a.n >= 64) gemm_first_x<TX>(a.X, a.ldx, a.N, Npad, a.vx, mu, x0, m0);
-    double pre[8];
-    if (small) {
+    const bool pre_x = a.n >= 64 && a.vx;
+    TX x0[16];
+    double m0[16], pre[8];
+    if (!small) stage_P(a.P64t, kn, sm_sp);
+    Partial p[8];
+    select_load(a, a.npass + nshort, 0, p);
+    // issued unconditionally (the 1/d^2 tiles serve as the spare source)
+    gemm_first_x<TX>(a.X, a.ldx, a.N, Npad, pre_x, a.invd2, mu, x0, m0);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) pre[u] = a.P64t[min((int)threadIdx.x + u * kPairBlock, kn - 1)];
-    } else {
-        stage_P(a.P64t, kn, sm_sp);
-    }
-    const int2 ij = select_min<K, TX, true>(a, a.npass + nshort, lead);
+    for (int u = 0; u < 8; ++u) pre[u] = a.P64t[min((int)threadIdx.x + u * kPairBlock, kn - 1)];
+    const int2 ij = select_min<K, TX, true>(a, a.npass + nshort, lead, p);
     if (small) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -1738,6 +1780,8 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
         for (int e = threadIdx.x; e < K * a.n; e += kPairBlock) Pn[e] = sm_sp[e];   // P unchanged
     }
     __syncthreads();
+    // X rows without 16-byte loads: the first chunk is loaded now (scalar)
+    if (a.n >= 64 && !pre_x) gemm_first_x_scalar<TX>(a.X, a.ldx, a.N, Npad, mu, x0, m0);
     gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, sm_sp, Y, a.Y64, a.kp, Npad, a.vx, (a.n & 1) == 0, x0, m0,
                    a.n >= 64, a.gemm);
 }

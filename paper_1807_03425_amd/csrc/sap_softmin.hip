@@ -151,8 +151,9 @@ __global__ __launch_bounds__(kPairBlock) void k_sm_prep(SmArgs a, const TX *__re
                                                         int gemm_blocks, int bwd) {
     if ((int)blockIdx.x < gemm_blocks)
     {
+        const TX nx[16] = {};
         const double none[16] = {};
-        gemm_block<TX>(X, ldx, N, a.n, K, mu, a.P64t, Y, nullptr, a.kp, Npad, a.vx, a.vp, none, none, false,
+        gemm_block<TX>(X, ldx, N, a.n, K, mu, a.P64t, Y, nullptr, a.kp, Npad, a.vx, a.vp, nx, none, false,
                        a.gemm);
     }
     else
