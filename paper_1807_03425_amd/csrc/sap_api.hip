@@ -942,7 +942,8 @@ sap_status sap_init(const sap_config *cfg, const void *X, int64_t ldx, const dou
     if (cfg->form == SAP_FUSED && (s = dalloc(h, &h->d_P64t_alt, sizeof(double) * h->n * h->k)) != SAP_OK)
         return bail(s);
     if ((s = load_P(h, P0)) != SAP_OK) return bail(s);
-    h->tail_lds = sizeof(double) * ((size_t)h->k * h->n + 2 * (size_t)h->n);
+    // P, the update's two vectors and (k_selprep's GEMM) the column means
+    h->tail_lds = sizeof(double) * ((size_t)h->k * h->n + 3 * (size_t)h->n);
     e = hipSuccess;
     SAP_DISPATCH_K(h->k, {
         e = KLaunch<K, float>::set_select_lds((int)h->tail_lds);

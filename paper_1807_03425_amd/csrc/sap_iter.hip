@@ -171,6 +171,7 @@ __device__ __forceinline__ void gemm_first_x(const TX *__restrict__ X, int64_t l
     load16_raw(xp, true, xa);
     load16_raw(mp, true, ma);
 }
+// The same without 16-byte loads (X rows not 16-byte aligned).
 template <typename TX>
 __device__ __forceinline__ void gemm_first_x_scalar(const TX *__restrict__ X, int64_t ldx, int64_t N, int64_t Npad,
                                                     const double *__restrict__ mu, TX (&xa)[16], double (&ma)[16]) {
@@ -281,7 +282,7 @@ __device__ __forceinline__ void gemm_block_lowp(const TX *__restrict__ X, int64_
 }
 
 // x0, m0 (used when use_x0): the first chunk's X values and means, loaded
-// earlier by gemm_first_x.  gemm: SAP_GEMM_F64 (below), or SAP_GEMM_F32 /
+// earlier by k_selprep.  gemm: SAP_GEMM_F64 (below), or SAP_GEMM_F32 /
 // SAP_GEMM_BF16 (gemm_block_lowp).  With the FP64 GEMM, Y64 (if not null)
 // receives the same products unrounded (the short-pair bounds use them).
 template <typename TX>
@@ -354,6 +355,72 @@ __device__ __forceinline__ void gemm_block(const TX *__restrict__ X, int64_t ldx
             if (m < k) b = pc[l];
         }
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    if (m < kp) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t r = row0 + kk + 4 * v;
+            const double y = (r < N && m < k) ? acc[v] : 0.0;
+            Y[r * kp + m] = (float)y;
+            if (Y64) Y64[r * kp + m] = y;
+        }
+    }
+}
+
+// The FP64 GEMM of gemm_block with P and the means in LDS and X streamed
+// from memory four 64-component chunks deep: the lane's slices of chunks
+// c + 1 .. c + 3 are in flight while chunk c's 16 MFMAs run, and the LDS
+// operands of chunk c + 1 are read during them, so a long chain of chunks is
+// bound by the matrix core rather than by one round trip per chunk.  X is
+// the only global source inside the loop, so the wait for chunk c (in issue
+// order) leaves the later chunks in flight.  Needs n a multiple of 256 and
+// 16-byte X rows; x0 holds chunk 0 (prefetched in X's type); loads past the
+// last chunk re-read it.  Rows past N and columns past k read valid
+// elements (row N - 1, column k - 1) and only feed outputs that are written
+// as zeros, so no operand is masked.
+template <typename TX>
+__device__ __forceinline__ void gemm_block_deep(const TX *__restrict__ X, int64_t ldx, int64_t N, int n, int k,
+                                                const double *mu_l, const double *P_l, float *__restrict__ Y,
+                                                double *__restrict__ Y64, int kp, int64_t Npad,
+                                                const TX (&x0)[16]) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (row0 >= Npad) return;
+    const int m = lane & 15, kk = lane >> 4;
+    const int64_t row = row0 + m;
+    const TX *xr = X + (row < N ? row : N - 1) * ldx + 16 * kk;
+    const double *pc = P_l + (m < k ? m : k - 1) * n + 16 * kk;
+    const double *mc = mu_l + 16 * kk;
+    const int nch = n >> 6;
+    TX xq[4][16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) xq[0][u] = x0[u];
+#pragma unroll
+    for (int c = 1; c < 4; ++c) load16_raw(xr + 64 * min(c, nch - 1), true, xq[c]);
+    double ml[2][16], pl[2][16];   // LDS operands of chunks c (slot c & 1) and c + 1
+    load16_raw(mc, true, ml[0]);
+    load16_raw(pc, true, pl[0]);
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int g = 0; g < nch; g += 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = g + r;
+            const int cn = min(c + 1, nch - 1);
+            load16_raw(mc + 64 * cn, true, ml[(r + 1) & 1]);
+            load16_raw(pc + 64 * cn, true, pl[(r + 1) & 1]);
+            double xa[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                TX t = xq[r][u];
+                asm volatile("" : "+v"(t));   // converted here, after chunk c has landed
+                xa[u] = (double)t;
+            }
+            load16_raw(xr + 64 * min(c + 4, nch - 1), true, xq[r]);
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s2] - ml[r & 1][s2], pl[r & 1][s2], acc, 0, 0, 0);
+        }
     }
     if (m < kp) {
 #pragma unroll
@@ -1748,16 +1815,23 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
     // selection waits for its own loads only, and these land meanwhile
     const int kn = K * a.n;
     const bool small = kn <= 8 * kPairBlock;
+    // the GEMM: four chunks deep with the means in LDS (FP64, 512 or 768 or
+    // 1024 components, 16-byte X rows), else gemm_block; either takes its
+    // first chunk prefetched here when X rows take 16-byte loads
     const bool pre_x = a.n >= 64 && a.vx;
+    const bool deep = pre_x && a.gemm == SAP_GEMM_F64 && a.n >= 512 && a.n <= 4 * kPairBlock && a.n % 256 == 0;
+    double *mu_l = sm_sp + (size_t)(K + 2) * a.n;   // past P and the update's two vectors
     TX x0[16];
-    double m0[16], pre[8];
-    if (!small) stage_P(a.P64t, kn, sm_sp);
+    double m0[16], pre[8], mpre[4];
     Partial p[8];
     select_load(a, a.npass + nshort, 0, p);
+    if (!small) stage_P(a.P64t, kn, sm_sp);
     // issued unconditionally (the 1/d^2 tiles serve as the spare source)
     gemm_first_x<TX>(a.X, a.ldx, a.N, Npad, pre_x, a.invd2, mu, x0, m0);
 #pragma unroll
     for (int u = 0; u < 8; ++u) pre[u] = a.P64t[min((int)threadIdx.x + u * kPairBlock, kn - 1)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) mpre[u] = mu[min((int)threadIdx.x + u * kPairBlock, a.n - 1)];
     const int2 ij = select_min<K, TX, true>(a, a.npass + nshort, lead, p);
     if (small) {
 #pragma unroll
@@ -1765,8 +1839,15 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
             const int e = (int)threadIdx.x + u * kPairBlock;
             if (e < kn) sm_sp[e] = pre[u];
         }
-        __syncthreads();
     }
+    if (deep) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = (int)threadIdx.x + u * kPairBlock;
+            if (e < a.n) mu_l[e] = mpre[u];
+        }
+    }
+    if (small || deep) __syncthreads();
     if (ij.x >= 0) {
         if (K <= 8 && a.n <= 64) {
             if (threadIdx.x < kWave)
@@ -1780,6 +1861,10 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
         for (int e = threadIdx.x; e < K * a.n; e += kPairBlock) Pn[e] = sm_sp[e];   // P unchanged
     }
     __syncthreads();
+    if (deep) {
+        gemm_block_deep<TX>(a.X, a.ldx, a.N, a.n, K, mu_l, sm_sp, Y, a.Y64, a.kp, Npad, x0);
+        return;
+    }
     // X rows without 16-byte loads: the first chunk is loaded now (scalar)
     if (a.n >= 64 && !pre_x) gemm_first_x_scalar<TX>(a.X, a.ldx, a.N, Npad, mu, x0, m0);
     gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, sm_sp, Y, a.Y64, a.kp, Npad, a.vx, (a.n & 1) == 0, x0, m0,
