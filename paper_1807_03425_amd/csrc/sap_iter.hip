@@ -1621,10 +1621,10 @@ __device__ __forceinline__ void apply_update(const TX *__restrict__ X, int64_t l
 }
 
 // The same update with the vectors in registers, for n <= 64 M (lane l owns
-// components l + 64 m) and small K M: every operation of apply_update, in the
-// same order per vector, but without LDS round trips, and with the
-// independent inner products of one step (c = P^T s; the projections of all
-// later vectors on q_m) reduced together, so their latencies overlap.
+// components l + 64 m) and small K M: the secant, c = P^T s, v and u as in
+// apply_update but without LDS round trips, and the Gram-Schmidt step on
+// coordinates in the basis P (see below), so that a step takes four
+// wavefront reductions instead of 2K + 4.
 template <int K, int M, typename TX>
 __device__ __forceinline__ void apply_update_reg(const TX *__restrict__ X, int64_t ldx, int n, double *Pl,
                                  double *__restrict__ P64t, void *__restrict__ Pr, int pr_kind,
@@ -1672,39 +1672,54 @@ __device__ __forceinline__ void apply_update_reg(const TX *__restrict__ X, int64
             for (int q = 0; q < K; ++q) acc = __builtin_fma(A[q][m], c[q], acc);
             v[m] = acc;
         }
-        // MGS input order (v, p_1..p_{t-1}, p_{t+1}..p_k): rows 1..t take
-        // rows 0..t-1 (selects, no dynamic register indexing)
+        // MGS of (v, p_1..p_{t-1}, p_{t+1}..p_k), carried out on their
+        // coordinates in the basis P: v = P c and p_q = P e_q, and P has
+        // orthonormal columns, so every inner product (hence every MGS
+        // coefficient) is that of the coordinate vectors.  The K x K
+        // coordinates (the same in every lane) take the place of the 2K
+        // wavefront reductions of the component form; the new vectors are
+        // P G.  G[j] is column j: c, then e_q for q = 0..k-1 without t.
+        double G[K][K];
 #pragma unroll
-        for (int q = K - 1; q >= 1; --q)
+        for (int jv = 0; jv < K; ++jv)
 #pragma unroll
-            for (int m = 0; m < M; ++m) A[q][m] = q <= t ? A[q - 1][m] : A[q][m];
-#pragma unroll
-        for (int m = 0; m < M; ++m) A[0][m] = v[m];
+            for (int r = 0; r < K; ++r)
+                G[jv][r] = jv == 0 ? c[r] : (r == (jv <= t ? jv - 1 : jv) ? 1.0 : 0.0);
         double vnorm = 0.0;
 #pragma unroll
         for (int mm = 0; mm < K; ++mm) {
             double nn = 0.0;
 #pragma unroll
-            for (int m = 0; m < M; ++m) nn = __builtin_fma(A[mm][m], A[mm][m], nn);
-            const double nrm = sqrt(wave_sum_fast(nn));
+            for (int r = 0; r < K; ++r) nn = __builtin_fma(G[mm][r], G[mm][r], nn);
+            const double nrm = sqrt(nn);
             if (mm == 0) vnorm = nrm;
+            const double rn = 1.0 / nrm;
 #pragma unroll
-            for (int m = 0; m < M; ++m) A[mm][m] = A[mm][m] / nrm;
-            double dots[K];
+            for (int r = 0; r < K; ++r) G[mm][r] = G[mm][r] * rn;
 #pragma unroll
-            for (int jv = 0; jv < K; ++jv) {
-                dots[jv] = 0.0;
-                if (jv > mm) {
+            for (int jv = mm + 1; jv < K; ++jv) {
+                double d = 0.0;
 #pragma unroll
-                    for (int m = 0; m < M; ++m) dots[jv] = __builtin_fma(A[mm][m], A[jv][m], dots[jv]);
-                }
+                for (int r = 0; r < K; ++r) d = __builtin_fma(G[mm][r], G[jv][r], d);
+#pragma unroll
+                for (int r = 0; r < K; ++r) G[jv][r] = G[jv][r] - d * G[mm][r];
             }
-            wave_sum_many<K>(dots, mm + 1);
-#pragma unroll
-            for (int jv = mm + 1; jv < K; ++jv)
-#pragma unroll
-                for (int m = 0; m < M; ++m) A[jv][m] = A[jv][m] - dots[jv] * A[mm][m];
         }
+        // q_2..q_k = P G[1..k-1] (q_1, v's direction, gives way to u below)
+        double Q[K][M];
+#pragma unroll
+        for (int jv = 1; jv < K; ++jv)
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < K; ++q) acc = __builtin_fma(A[q][m], G[jv][q], acc);
+                Q[jv][m] = acc;
+            }
+#pragma unroll
+        for (int jv = 1; jv < K; ++jv)
+#pragma unroll
+            for (int m = 0; m < M; ++m) A[jv][m] = Q[jv][m];
         double wn = 1.0;
         if (rule == SAP_STEP_NORMALIZED) {
             double acc = 0.0;
