@@ -1416,6 +1416,40 @@ __global__ __launch_bounds__(kPairBlock) void k_prep(SweepArgs<TX> a, const doub
 
 // ------------------------------------------------------------------ the update
 
+// The modified Gram-Schmidt step of the update on coordinates in the basis
+// P: the columns are c (v = P c) and e_q for q = 0..k-1 without t (the kept
+// columns p_q = P e_q), in that order; since P has orthonormal columns,
+// every inner product, hence every coefficient, equals that of the vectors
+// themselves, and the orthonormalised vectors are P G[j].  vnorm = |c| =
+// |v|.  Uniform: every lane computes the same K x K values.
+template <int K>
+__device__ __forceinline__ void coord_mgs(const double (&c)[K], int t, double (&G)[K][K], double &vnorm) {
+#pragma unroll
+    for (int jv = 0; jv < K; ++jv)
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+            G[jv][r] = jv == 0 ? c[r] : (r == (jv <= t ? jv - 1 : jv) ? 1.0 : 0.0);
+#pragma unroll
+    for (int mm = 0; mm < K; ++mm) {
+        double nn = 0.0;
+#pragma unroll
+        for (int r = 0; r < K; ++r) nn = __builtin_fma(G[mm][r], G[mm][r], nn);
+        const double nrm = sqrt(nn);
+        if (mm == 0) vnorm = nrm;
+        const double rn = 1.0 / nrm;
+#pragma unroll
+        for (int r = 0; r < K; ++r) G[mm][r] = G[mm][r] * rn;
+#pragma unroll
+        for (int jv = mm + 1; jv < K; ++jv) {
+            double d = 0.0;
+#pragma unroll
+            for (int r = 0; r < K; ++r) d = __builtin_fma(G[mm][r], G[jv][r], d);
+#pragma unroll
+            for (int r = 0; r < K; ++r) G[jv][r] = G[jv][r] - d * G[mm][r];
+        }
+    }
+}
+
 // v + (v of the exchange partner at distance 2^S inside the wavefront):
 // quad xor 1, quad xor 2, 16-lane rotation by 4 (the partner differs in bit
 // 2 and agrees below it), rotation by 8 (xor 8), then the permlane swaps.
@@ -1493,13 +1527,15 @@ __device__ __forceinline__ double block_sum(double x, double (*red)[kPairBlock /
 //               P' = [u, q_2, .., q_k]
 // The vectors live in LDS (A: K x n, then s, v); thread x owns components
 // x, x+256, ... of every vector and is the only one to touch them, so the
-// vectors need no barriers; every inner product is a block sum.  Modified
-// Gram-Schmidt runs right-looking: once q_m is final, every later vector
-// loses its component along q_m (per vector, the same sequence of
-// subtractions as the column-by-column form).  The independent inner
-// products of one step (the K entries of c; the projections of all later
-// vectors on q_m) are reduced together, so a step waits on two reductions
-// (|a_m| and the batch).  Every thread of the block must call this.
+// vectors need no barriers; every inner product is a block sum.  For K <= 8
+// the Gram-Schmidt step runs on coordinates in the basis P (coord_mgs): no
+// block sum, and the new vectors are P G.  For larger K it runs on the
+// vectors, right-looking: once q_m is final, every later vector loses its
+// component along q_m (per vector, the same sequence of subtractions as the
+// column-by-column form), and the independent inner products of one step
+// (the projections of all later vectors on q_m) are reduced together, so a
+// step waits on two reductions (|a_m| and the batch).  Every thread of the
+// block must call this.
 template <int K, typename TX>
 __device__ __forceinline__ void apply_update(const TX *__restrict__ X, int64_t ldx, int n,
                              double *__restrict__ P64t, void *__restrict__ Pr, int pr_kind,
@@ -1539,47 +1575,73 @@ __device__ __forceinline__ void apply_update(const TX *__restrict__ X, int64_t l
     if (cmax == 0.0) {
         for (int l = tid; l < n; l += kPairBlock) A[l] = s[l];
     } else {
-        // v = P c; MGS input order (v, p_1..p_{t-1}, p_{t+1}..p_k), in place
-        for (int l = tid; l < n; l += kPairBlock) {
-            double acc = 0.0;
-#pragma unroll
-            for (int q = 0; q < K; ++q) acc = __builtin_fma(A[(size_t)q * n + l], c[q], acc);
-            v[l] = acc;
-            for (int m = t; m > 0; --m) A[(size_t)m * n + l] = A[(size_t)(m - 1) * n + l];
-            A[l] = acc;
-        }
         double vnorm = 0.0;
-#pragma unroll 1
-        for (int m = 0; m < K; ++m) {
-            double *am = A + (size_t)m * n;
-            double nn = 0.0;
-            for (int l = tid; l < n; l += kPairBlock) nn = __builtin_fma(am[l], am[l], nn);
-            const double nrm = sqrt(block_sum(nn, red, ph));
-            if (m == 0) vnorm = nrm;
-            if (m + 1 == K) {
-                for (int l = tid; l < n; l += kPairBlock) am[l] = am[l] / nrm;
-                break;
-            }
-            // every row's inner product with q_m, without branches (rows
-            // up to m are final: their products go unused and the select
-            // below rewrites them unchanged)
-            double dots[K];
-#pragma unroll
-            for (int jv = 0; jv < K; ++jv) dots[jv] = 0.0;
+        if constexpr (K <= 8) {
+            // v = P c; the Gram-Schmidt step on coordinates in the basis P
+            // (as in apply_update_reg, the K x K coordinates the same in
+            // every thread), then q_2..q_k = P G[1..k-1] in place
             for (int l = tid; l < n; l += kPairBlock) {
-                const double q = am[l] / nrm;
-                am[l] = q;
+                double acc = 0.0;
 #pragma unroll
-                for (int jv = 0; jv < K; ++jv) dots[jv] = __builtin_fma(q, A[(size_t)jv * n + l], dots[jv]);
+                for (int q = 0; q < K; ++q) acc = __builtin_fma(A[(size_t)q * n + l], c[q], acc);
+                v[l] = acc;
             }
-            block_sum_many<K>(dots, red, ph);
+            double G[K][K];
+            coord_mgs<K>(c, t, G, vnorm);
             for (int l = tid; l < n; l += kPairBlock) {
-                const double q = am[l];
                 double x[K];   // every row read before any is written back
 #pragma unroll
-                for (int jv = 0; jv < K; ++jv) x[jv] = A[(size_t)jv * n + l];
+                for (int q = 0; q < K; ++q) x[q] = A[(size_t)q * n + l];
 #pragma unroll
-                for (int jv = 0; jv < K; ++jv) A[(size_t)jv * n + l] = jv > m ? x[jv] - dots[jv] * q : x[jv];
+                for (int jv = 1; jv < K; ++jv) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int q = 0; q < K; ++q) acc = __builtin_fma(x[q], G[jv][q], acc);
+                    A[(size_t)jv * n + l] = acc;
+                }
+            }
+        } else {
+            // v = P c; MGS input order (v, p_1..p_{t-1}, p_{t+1}..p_k), in place
+            for (int l = tid; l < n; l += kPairBlock) {
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < K; ++q) acc = __builtin_fma(A[(size_t)q * n + l], c[q], acc);
+                v[l] = acc;
+                for (int m = t; m > 0; --m) A[(size_t)m * n + l] = A[(size_t)(m - 1) * n + l];
+                A[l] = acc;
+            }
+#pragma unroll 1
+            for (int m = 0; m < K; ++m) {
+                double *am = A + (size_t)m * n;
+                double nn = 0.0;
+                for (int l = tid; l < n; l += kPairBlock) nn = __builtin_fma(am[l], am[l], nn);
+                const double nrm = sqrt(block_sum(nn, red, ph));
+                if (m == 0) vnorm = nrm;
+                if (m + 1 == K) {
+                    for (int l = tid; l < n; l += kPairBlock) am[l] = am[l] / nrm;
+                    break;
+                }
+                // every row's inner product with q_m, without branches (rows
+                // up to m are final: their products go unused and the select
+                // below rewrites them unchanged)
+                double dots[K];
+#pragma unroll
+                for (int jv = 0; jv < K; ++jv) dots[jv] = 0.0;
+                for (int l = tid; l < n; l += kPairBlock) {
+                    const double q = am[l] / nrm;
+                    am[l] = q;
+#pragma unroll
+                    for (int jv = 0; jv < K; ++jv) dots[jv] = __builtin_fma(q, A[(size_t)jv * n + l], dots[jv]);
+                }
+                block_sum_many<K>(dots, red, ph);
+                for (int l = tid; l < n; l += kPairBlock) {
+                    const double q = am[l];
+                    double x[K];   // every row read before any is written back
+#pragma unroll
+                    for (int jv = 0; jv < K; ++jv) x[jv] = A[(size_t)jv * n + l];
+#pragma unroll
+                    for (int jv = 0; jv < K; ++jv) A[(size_t)jv * n + l] = jv > m ? x[jv] - dots[jv] * q : x[jv];
+                }
             }
         }
         // the alpha shift toward the worst secant
@@ -1672,39 +1734,11 @@ __device__ __forceinline__ void apply_update_reg(const TX *__restrict__ X, int64
             for (int q = 0; q < K; ++q) acc = __builtin_fma(A[q][m], c[q], acc);
             v[m] = acc;
         }
-        // MGS of (v, p_1..p_{t-1}, p_{t+1}..p_k), carried out on their
-        // coordinates in the basis P: v = P c and p_q = P e_q, and P has
-        // orthonormal columns, so every inner product (hence every MGS
-        // coefficient) is that of the coordinate vectors.  The K x K
-        // coordinates (the same in every lane) take the place of the 2K
-        // wavefront reductions of the component form; the new vectors are
-        // P G.  G[j] is column j: c, then e_q for q = 0..k-1 without t.
+        // MGS of (v, p_1..p_{t-1}, p_{t+1}..p_k) on coordinates in the basis
+        // P (coord_mgs): no wavefront reduction, and the new vectors are P G
         double G[K][K];
-#pragma unroll
-        for (int jv = 0; jv < K; ++jv)
-#pragma unroll
-            for (int r = 0; r < K; ++r)
-                G[jv][r] = jv == 0 ? c[r] : (r == (jv <= t ? jv - 1 : jv) ? 1.0 : 0.0);
         double vnorm = 0.0;
-#pragma unroll
-        for (int mm = 0; mm < K; ++mm) {
-            double nn = 0.0;
-#pragma unroll
-            for (int r = 0; r < K; ++r) nn = __builtin_fma(G[mm][r], G[mm][r], nn);
-            const double nrm = sqrt(nn);
-            if (mm == 0) vnorm = nrm;
-            const double rn = 1.0 / nrm;
-#pragma unroll
-            for (int r = 0; r < K; ++r) G[mm][r] = G[mm][r] * rn;
-#pragma unroll
-            for (int jv = mm + 1; jv < K; ++jv) {
-                double d = 0.0;
-#pragma unroll
-                for (int r = 0; r < K; ++r) d = __builtin_fma(G[mm][r], G[jv][r], d);
-#pragma unroll
-                for (int r = 0; r < K; ++r) G[jv][r] = G[jv][r] - d * G[mm][r];
-            }
-        }
+        coord_mgs<K>(c, t, G, vnorm);
         // q_2..q_k = P G[1..k-1] (q_1, v's direction, gives way to u below)
         double Q[K][M];
 #pragma unroll
