@@ -84,6 +84,9 @@ struct sap_ctx {
     Partial *d_part = nullptr;   // pass-block results, then one per short-pair block
     DevResult *d_res = nullptr;
     int pass_grid = 0, short_grid = 0;
+    // fused FP64 Y GEMM split over two wavefronts per 16-row tile (k_prep and
+    // k_selprep run n_pad / 32 blocks; see gemm_block_deep)
+    bool gemm_split = false;
     int short_grid_it = 0;   // short-pair blocks of the iteration's pass (<= short_grid)
     int sm_grid = 0;   // fused: blocks of the soft-min tile passes
     size_t tail_lds = 0;
@@ -475,6 +478,10 @@ static sap_status init_fused(sap_ctx *h) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
         cus = 256;
     const int64_t slots = 4 * (int64_t)cus;
+    // the split GEMM: 512 or 1024 components, 16-byte X rows, FP64, and fewer
+    // 64-row blocks than compute units (the split doubles them)
+    h->gemm_split = h->cfg.gemm == SAP_GEMM_F64 && h->vec_x && (h->n == 512 || h->n == 1024) &&
+                    h->Npad / 64 < cus;
     h->pass_grid = (int)std::max<int64_t>(
         1, std::min<int64_t>(ceil_div(2 * h->ntiles, 4), std::max<int64_t>(slots / 4, slots - h->short_grid_it)));
     // soft-min tile passes (three or four blocks per compute unit): eight
@@ -566,6 +573,7 @@ static SweepArgs<TX> sweep_args(sap_ctx *h, double *tr_min, int64_t *tr_ij, int3
     a.it = it;
     a.cap = h->cfg.cand_cap > 0 ? h->cfg.cand_cap : kCandCap;
     a.gemm = h->cfg.gemm;
+    a.split = h->gemm_split ? 1 : 0;
     return a;
 }
 
@@ -574,8 +582,10 @@ template <typename TX>
 static sap_status launch_prep(sap_ctx *h) {
     const int K = h->k;
     const SweepArgs<TX> a = sweep_args<TX>(h, nullptr, nullptr, nullptr, 0);
-    const dim3 g0((unsigned)(h->Npad / 64)), blk(kPairBlock);
-    SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 0, "k_prep", g0, blk, 0, [&](const LaunchCfg &c) {
+    const dim3 g0((unsigned)(h->Npad / (h->gemm_split ? 32 : 64))), blk(kPairBlock);
+    // the split GEMM keeps P, the means and 512 exchange slots in LDS
+    const uint32_t lds = h->gemm_split ? (uint32_t)(sizeof(double) * ((size_t)(K + 1) * h->n + 512)) : 0u;
+    SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 0, "k_prep", g0, blk, lds, [&](const LaunchCfg &c) {
         return KLaunch<K, TX>::prep(c, a, h->d_mu, h->d_Y, h->Npad);
     })));
     return SAP_OK;
@@ -618,7 +628,7 @@ template <typename TX>
 static sap_status launch_selprep(sap_ctx *h, double *tr_min, int64_t *tr_ij, int32_t *tr_cert, int it) {
     const int K = h->k;
     const SweepArgs<TX> a = sweep_args<TX>(h, tr_min, tr_ij, tr_cert, it);
-    const dim3 g0((unsigned)(h->Npad / 64)), blk(kPairBlock);
+    const dim3 g0((unsigned)(h->Npad / (h->gemm_split ? 32 : 64))), blk(kPairBlock);
     SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 6, "k_selprep", g0, blk, (uint32_t)h->tail_lds,
                                           [&](const LaunchCfg &c) {
         return KLaunch<K, TX>::selprep(c, a, h->short_grid_it, h->d_P64t_alt, h->cfg.alpha, h->cfg.rule,
@@ -644,7 +654,8 @@ static sap_status launch_iteration(sap_ctx *h, int do_step, double *tr_min, int6
 // per iteration) keep the three launches.
 template <typename TX>
 static sap_status launch_run(sap_ctx *h, int32_t iters, double *tr_min, int64_t *tr_ij, int32_t *tr_cert) {
-    const int64_t reads = (h->Npad / 64) * (int64_t)(h->pass_grid + h->short_grid_it) * (int64_t)sizeof(Partial);
+    const int64_t reads = (h->Npad / (h->gemm_split ? 32 : 64)) * (int64_t)(h->pass_grid + h->short_grid_it) *
+                          (int64_t)sizeof(Partial);
     if (h->cfg.form != SAP_FUSED || reads > (16 << 20)) {
         for (int32_t it = 0; it <= iters; ++it)
             SAP_TRY(launch_iteration<TX>(h, it < iters ? 1 : 0, tr_min, tr_ij, tr_cert, it));

@@ -160,14 +160,13 @@ __device__ __forceinline__ void load16_raw(const T *__restrict__ p, bool vec, T 
 // when not): with no branch around them, the wait for loads issued earlier
 // stays exact.
 template <typename TX>
-__device__ __forceinline__ void gemm_first_x(const TX *__restrict__ X, int64_t ldx, int64_t N, int64_t Npad,
-                                             bool use, const void *spare, const double *__restrict__ mu,
+__device__ __forceinline__ void gemm_first_x(const TX *__restrict__ X, int64_t ldx, int64_t N, int64_t row0,
+                                             int l0, bool use, const void *spare, const double *__restrict__ mu,
                                              TX (&xa)[16], double (&ma)[16]) {
     const int lane = threadIdx.x & 63;
-    const int64_t row0 = min(((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16, Npad - 16);
     const int64_t row = row0 + (lane & 15);
-    const TX *xp = use ? X + (row < N ? row : N - 1) * ldx + 16 * (lane >> 4) : static_cast<const TX *>(spare);
-    const double *mp = use ? mu + 16 * (lane >> 4) : static_cast<const double *>(spare);
+    const TX *xp = use ? X + (row < N ? row : N - 1) * ldx + l0 + 16 * (lane >> 4) : static_cast<const TX *>(spare);
+    const double *mp = use ? mu + l0 + 16 * (lane >> 4) : static_cast<const double *>(spare);
     load16_raw(xp, true, xa);
     load16_raw(mp, true, ma);
 }
@@ -367,6 +366,21 @@ __device__ __forceinline__ void gemm_block(const TX *__restrict__ X, int64_t ldx
     }
 }
 
+// The 16-row tile (first row row0) and the range of 64-component chunks
+// [cb, cb + nch) of the calling wavefront in gemm_block_deep.
+__device__ __forceinline__ void deep_tile(bool split, int n, int64_t &row0, int &cb, int &nch) {
+    const int w = threadIdx.x >> 6;
+    if (split) {
+        row0 = ((int64_t)blockIdx.x * 2 + (w & 1)) * 16;
+        nch = n >> 7;
+        cb = (w >> 1) * nch;
+    } else {
+        row0 = ((int64_t)blockIdx.x * 4 + w) * 16;
+        nch = n >> 6;
+        cb = 0;
+    }
+}
+
 // The FP64 GEMM of gemm_block with P and the means in LDS and X streamed
 // from memory four 64-component chunks deep: the lane's slices of chunks
 // c + 1 .. c + 3 are in flight while chunk c's 16 MFMAs run, and the LDS
@@ -374,24 +388,32 @@ __device__ __forceinline__ void gemm_block(const TX *__restrict__ X, int64_t ldx
 // bound by the matrix core rather than by one round trip per chunk.  X is
 // the only global source inside the loop, so the wait for chunk c (in issue
 // order) leaves the later chunks in flight.  Needs n a multiple of 256 and
-// 16-byte X rows; x0 holds chunk 0 (prefetched in X's type); loads past the
-// last chunk re-read it.  Rows past N and columns past k read valid
-// elements (row N - 1, column k - 1) and only feed outputs that are written
-// as zeros, so no operand is masked.
+// 16-byte X rows; x0 holds the wavefront's first chunk (prefetched in X's
+// type, see deep_tile); loads past the last chunk re-read it.  Rows past N
+// and columns past k read valid elements (row N - 1, column k - 1) and only
+// feed outputs that are written as zeros, so no operand is masked.
+//
+// split (n a multiple of 512): a block covers 32 rows, and the wavefronts
+// w and w + 2 share a 16-row tile, each taking half of the chunks; the
+// second half's sums go through xch (LDS, 512 doubles) and are added to the
+// first's (twice the blocks, half the chain per wavefront).  Every thread of
+// the block must call it then.  A GEMM's rows are all computed one way or
+// the other, so results do not depend on the kernel that computes them.
 template <typename TX>
 __device__ __forceinline__ void gemm_block_deep(const TX *__restrict__ X, int64_t ldx, int64_t N, int n, int k,
                                                 const double *mu_l, const double *P_l, float *__restrict__ Y,
                                                 double *__restrict__ Y64, int kp, int64_t Npad,
-                                                const TX (&x0)[16]) {
-    const int lane = threadIdx.x & 63;
-    const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-    if (row0 >= Npad) return;
+                                                const TX (&x0)[16], bool split, double *xch) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t row0;
+    int cb, nch;
+    deep_tile(split, n, row0, cb, nch);
+    if (!split && row0 >= Npad) return;
     const int m = lane & 15, kk = lane >> 4;
     const int64_t row = row0 + m;
-    const TX *xr = X + (row < N ? row : N - 1) * ldx + 16 * kk;
-    const double *pc = P_l + (m < k ? m : k - 1) * n + 16 * kk;
-    const double *mc = mu_l + 16 * kk;
-    const int nch = n >> 6;
+    const TX *xr = X + (row < N ? row : N - 1) * ldx + 64 * cb + 16 * kk;
+    const double *pc = P_l + (m < k ? m : k - 1) * n + 64 * cb + 16 * kk;
+    const double *mc = mu_l + 64 * cb + 16 * kk;
     TX xq[4][16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) xq[0][u] = x0[u];
@@ -421,6 +443,18 @@ __device__ __forceinline__ void gemm_block_deep(const TX *__restrict__ X, int64_
             for (int s2 = 0; s2 < 16; ++s2)
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s2] - ml[r & 1][s2], pl[r & 1][s2], acc, 0, 0, 0);
         }
+    }
+    if (split) {
+        // the second half's sums, added to the first's in a fixed order
+        double *xs = xch + ((w & 1) * kWave + lane) * 4;
+        if (w >= 2) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xs[v] = acc[v];
+        }
+        __syncthreads();
+        if (w >= 2) return;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = acc[v] + xs[v];
     }
     if (m < kp) {
 #pragma unroll
@@ -770,6 +804,8 @@ struct SweepArgs {
     int it;
     int cap;              // candidate-list capacity per wavefront, 1..kCandCap
     int gemm;             // arithmetic of the Y GEMM: SAP_GEMM_F64 | _F32 | _BF16
+    int split;            // Y GEMM split over two wavefronts per tile (gemm_block_deep): k_prep
+                          // and k_selprep then run n_pad / 32 blocks
 };
 
 // Candidates of a pass block.  The block keeps its running minimum key in
@@ -1404,10 +1440,46 @@ __global__ __launch_bounds__(kPairBlock, (FUSED || sizeof(TX) == 4 || K <= 12) ?
     else plain_pass_block<K, TX>(a, pb);
 }
 
+// The K x n FP64 P into LDS, eight loads in flight per thread before any
+// is stored.
+__device__ __forceinline__ void stage_P(const double *__restrict__ P, int kn, double *sm) {
+#pragma unroll 1
+    for (int e0 = threadIdx.x; e0 < kn; e0 += 8 * kPairBlock) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kPairBlock;
+            t[u] = e < kn ? P[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kPairBlock;
+            if (e < kn) sm[e] = t[u];
+        }
+    }
+}
+
 // Fused form, before the pass: Y = (X - mu) P.
 template <int K, typename TX>
 __global__ __launch_bounds__(kPairBlock) void k_prep(SweepArgs<TX> a, const double *__restrict__ mu,
                                                      float *__restrict__ Y, int64_t Npad) {
+    if (a.split) {
+        // the split GEMM of k_selprep (the same tiles and order of sums):
+        // P, the means and the exchange slots in LDS
+        extern __shared__ __align__(16) double sm_pp[];
+        int64_t row0;
+        int cb, nch;
+        deep_tile(true, a.n, row0, cb, nch);
+        TX x0[16];
+        double m0[16];
+        gemm_first_x<TX>(a.X, a.ldx, a.N, row0, 64 * cb, true, a.invd2, mu, x0, m0);
+        stage_P(a.P64t, K * a.n, sm_pp);
+        double *mu_l = sm_pp + (size_t)K * a.n;
+        for (int e = threadIdx.x; e < a.n; e += kPairBlock) mu_l[e] = mu[e];
+        __syncthreads();
+        gemm_block_deep<TX>(a.X, a.ldx, a.N, a.n, K, mu_l, sm_pp, Y, a.Y64, a.kp, Npad, x0, true, mu_l + a.n);
+        return;
+    }
     const TX nx[16] = {};
     const double none[16] = {};
     gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, a.P64t, Y, a.Y64, a.kp, Npad, a.vx, a.vp, nx, none, false,
@@ -1796,24 +1868,6 @@ __device__ __forceinline__ void apply_update_reg(const TX *__restrict__ X, int64
     }
 }
 
-// The K x n FP64 P into LDS, eight loads in flight per thread before any
-// is stored.
-__device__ __forceinline__ void stage_P(const double *__restrict__ P, int kn, double *sm) {
-#pragma unroll 1
-    for (int e0 = threadIdx.x; e0 < kn; e0 += 8 * kPairBlock) {
-        double t[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * kPairBlock;
-            t[u] = e < kn ? P[e] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * kPairBlock;
-            if (e < kn) sm[e] = t[u];
-        }
-    }
-}
 
 // Selection, record and (do_step) update, in one block.  Dynamic LDS holds
 // P (read by the rescoring, then the update's working copy) and the update's
@@ -1875,8 +1929,17 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
     Partial p[8];
     select_load(a, a.npass + nshort, 0, p);
     if (!small) stage_P(a.P64t, kn, sm_sp);
-    // issued unconditionally (the 1/d^2 tiles serve as the spare source)
-    gemm_first_x<TX>(a.X, a.ldx, a.N, Npad, pre_x, a.invd2, mu, x0, m0);
+    // the wavefront's first chunk of X and the matching means, issued
+    // unconditionally (the 1/d^2 tiles serve as the spare source)
+    const bool split = deep && a.split;
+    int64_t row0 = min(((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16, Npad - 16);
+    int l0 = 0;
+    if (deep) {
+        int cb, nch;
+        deep_tile(split, a.n, row0, cb, nch);
+        l0 = 64 * cb;
+    }
+    gemm_first_x<TX>(a.X, a.ldx, a.N, row0, l0, pre_x, a.invd2, mu, x0, m0);
 #pragma unroll
     for (int u = 0; u < 8; ++u) pre[u] = a.P64t[min((int)threadIdx.x + u * kPairBlock, kn - 1)];
 #pragma unroll
@@ -1911,7 +1974,9 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
     }
     __syncthreads();
     if (deep) {
-        gemm_block_deep<TX>(a.X, a.ldx, a.N, a.n, K, mu_l, sm_sp, Y, a.Y64, a.kp, Npad, x0);
+        // (the update's vector s, past P, holds the split's exchange slots)
+        gemm_block_deep<TX>(a.X, a.ldx, a.N, a.n, K, mu_l, sm_sp, Y, a.Y64, a.kp, Npad, x0, split,
+                            sm_sp + (size_t)K * a.n);
         return;
     }
     // X rows without 16-byte loads: the first chunk is loaded now (scalar)

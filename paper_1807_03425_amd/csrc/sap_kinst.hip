@@ -53,9 +53,10 @@ hipError_t KLaunch<K, TX>::selprep(const LaunchCfg &c, const SweepArgs<TX> &a, i
 
 template <int K, typename TX>
 hipError_t KLaunch<K, TX>::set_select_lds(int bytes) {
-    const void *fns[3] = {reinterpret_cast<const void *>(&k_select<K, TX, true>),
+    const void *fns[4] = {reinterpret_cast<const void *>(&k_select<K, TX, true>),
                           reinterpret_cast<const void *>(&k_select<K, TX, false>),
-                          reinterpret_cast<const void *>(&k_selprep<K, TX>)};
+                          reinterpret_cast<const void *>(&k_selprep<K, TX>),
+                          reinterpret_cast<const void *>(&k_prep<K, TX>)};
     for (const void *f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;

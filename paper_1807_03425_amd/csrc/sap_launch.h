@@ -26,7 +26,7 @@ struct KLaunch {
                              double *P64t, void *Pr, int pr_kind, double alpha, int rule, int do_step);
     static hipError_t selprep(const LaunchCfg &c, const SweepArgs<TX> &a, int nshort, double *Pn,
                               double alpha, int rule, const double *mu, float *Y, int64_t Npad);
-    // dynamic LDS limit of the selection kernels (bytes)
+    // dynamic LDS limit of the selection kernels and of k_prep (bytes)
     static hipError_t set_select_lds(int bytes);
     // the soft-min (sap_softmin.hip)
     static hipError_t sm_prep(const LaunchCfg &c, const SmArgs &a, const TX *X, int64_t ldx, int64_t N,
