@@ -976,47 +976,57 @@ __device__ __forceinline__ uint32_t block_run_min(uint32_t *s_run, uint32_t m) {
     return old < m ? old : m;
 }
 
-// After the pass loop: keep the candidates with key <= T2b, rescore them.
-template <int K, typename TX>
-__device__ __forceinline__ void rescore_cands(const SweepArgs<TX> &a, const CandList &cl, uint32_t T2b,
-                                              WaveBest &wb) {
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll 1
-    for (int c = 0; c < cl.n; ++c) {
-        const uint32_t kv = cl.key[c];
-        if (kv > T2b) continue;
-        const int2 ij = cl.ij[c];
-        double r;
-        // one group of components when n <= 64 (no clamped extra loads; K <= 7,
-        // where the second instance fits the register budget)
-        if (K <= 7 && a.n <= kWave) r = exact_r_wave<K, TX, 1>(a.X, a.ldx, a.n, a.P64t, ij.x, ij.y);
-        else r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, a.P64t, ij.x, ij.y);
-        ++wb.nwin;
-        wb.nviol += bound_broken(r, (double)__uint_as_float(kv), a.e_abs, a.e_rel);
-        if (lex_less(r, ij.x, ij.y, wb.r, wb.i, wb.j)) {
-            wb.r2 = wb.r;
-            wb.r = r; wb.i = ij.x; wb.j = ij.y;
-        } else {
-            wb.r2 = fmin(wb.r2, r);
-        }
-    }
-}
-
-// Block minimum of the wavefronts' coarse minima (uniform per wavefront),
-// then every wavefront rescores its surviving candidates, and the block's
-// result goes to its Partial slot.
+// After every wavefront's sweep: the block's final minimum, then the four
+// wavefronts share the rescoring of the block's candidates inside its window
+// (every fourth entry of the four lists taken together, so that one long
+// list does not hold the block back), and the block's result goes to its
+// Partial slot.  The block window contains the window of the pass's global
+// minimum, so every pair of the latter is rescored.  Every thread of the
+// block must call it.
 template <int K, typename TX>
 __device__ __forceinline__ void finish_pass_block(const SweepArgs<TX> &a, const CandList &cl,
                                                   uint32_t kmin, const uint32_t *s_run, WaveBest &wb,
+                                                  const int2 (*cij)[kCandCap], const uint32_t (*ckey)[kCandCap],
                                                   Partial *out) {
-    // rescore now, against the window of the block's running minimum as it
-    // stands (never below the final block minimum, so this covers the block
-    // window's share of the list), overlapping the sweeps of the block's
-    // other wavefronts
-    const uint32_t run = __builtin_amdgcn_readfirstlane(*(const volatile uint32_t *)s_run);
-    if (run < 0x7f800000u) rescore_cands<K, TX>(a, cl, item_window(run, a.wa, a.wb), wb);
-    wb.nviol += cl.lost;   // dropped candidates: the result is not certified
+    __shared__ int s_cn[kPairBlock / kWave];
     const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (lane == 0) s_cn[wv] = cl.n;
+    __syncthreads();   // every list and the block minimum are final
+    const uint32_t run = __builtin_amdgcn_readfirstlane(*(const volatile uint32_t *)s_run);
+    if (run < 0x7f800000u) {
+        const uint32_t T2b = item_window(run, a.wa, a.wb);
+        const int n0 = s_cn[0], n1 = s_cn[1], n2 = s_cn[2], n3 = s_cn[3];
+        const int tot = n0 + n1 + n2 + n3;
+#pragma unroll 1
+        for (int g = wv; g < tot; g += kPairBlock / kWave) {
+            int L = 0, c = g;   // (list, entry) of the g-th candidate (wavefront-uniform)
+            if (c >= n0) {
+                c -= n0; L = 1;
+                if (c >= n1) {
+                    c -= n1; L = 2;
+                    if (c >= n2) { c -= n2; L = 3; }
+                }
+            }
+            const uint32_t kv = ckey[L][c];
+            if (kv > T2b) continue;
+            const int2 ij = cij[L][c];
+            double r;
+            // one group of components when n <= 64 (no clamped extra loads;
+            // K <= 7, where the second instance fits the register budget)
+            if (K <= 7 && a.n <= kWave) r = exact_r_wave<K, TX, 1>(a.X, a.ldx, a.n, a.P64t, ij.x, ij.y);
+            else r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, a.P64t, ij.x, ij.y);
+            ++wb.nwin;
+            wb.nviol += bound_broken(r, (double)__uint_as_float(kv), a.e_abs, a.e_rel);
+            if (lex_less(r, ij.x, ij.y, wb.r, wb.i, wb.j)) {
+                wb.r2 = wb.r;
+                wb.r = r; wb.i = ij.x; wb.j = ij.y;
+            } else {
+                wb.r2 = fmin(wb.r2, r);
+            }
+        }
+    }
+    wb.nviol += cl.lost;   // dropped candidates: the result is not certified
     block_reduce_partial(wb.r, wb.i, wb.j, wb.r2, lane == 0 ? wb.nwin : 0, lane == 0 ? wb.nunits : 0,
                          lane == 0 ? wb.nviol : 0, kmin, cl.limit, out, false);
 }
@@ -1116,7 +1126,7 @@ __device__ void fused_pass_block(const SweepArgs<TX> &a, int pb) {
         __builtin_amdgcn_wave_barrier();
         if (h + nw < nitem) fetch(h + nw);       // the next item's loads
     }
-    finish_pass_block<K, TX>(a, cl, kmin, &s_run, wb, a.part + pb);
+    finish_pass_block<K, TX>(a, cl, kmin, &s_run, wb, s_cij, s_ckey, a.part + pb);
 }
 
 // Plain pass block: one wavefront per 256-pair chunk (grid-stride), the
@@ -1155,7 +1165,7 @@ __device__ void plain_pass_block(const SweepArgs<TX> &a, int pb) {
                        },
                        wb);
     }
-    finish_pass_block<K, TX>(a, cl, kmin, &s_run, wb, a.part + pb);
+    finish_pass_block<K, TX>(a, cl, kmin, &s_run, wb, s_cij, s_ckey, a.part + pb);
 }
 
 // c = P^T (x_i - x_j) for 16 short pairs in FP64 on the matrix cores, tiled
