@@ -1609,7 +1609,7 @@ __device__ __forceinline__ double block_sum(double x, double (*red)[kPairBlock /
 //               P' = [u, q_2, .., q_k]
 // The vectors live in LDS (A: K x n, then s, v); thread x owns components
 // x, x+256, ... of every vector and is the only one to touch them, so the
-// vectors need no barriers; every inner product is a block sum.  For K <= 8
+// vectors need no barriers; every inner product is a block sum.  For K <= 12
 // the Gram-Schmidt step runs on coordinates in the basis P (coord_mgs): no
 // block sum, and the new vectors are P G.  For larger K it runs on the
 // vectors, right-looking: once q_m is final, every later vector loses its
@@ -1658,7 +1658,7 @@ __device__ __forceinline__ void apply_update(const TX *__restrict__ X, int64_t l
         for (int l = tid; l < n; l += kPairBlock) A[l] = s[l];
     } else {
         double vnorm = 0.0;
-        if constexpr (K <= 8) {
+        if constexpr (K <= 12) {
             // v = P c; the Gram-Schmidt step on coordinates in the basis P
             // (as in apply_update_reg, the K x K coordinates the same in
             // every thread), then q_2..q_k = P G[1..k-1] in place
