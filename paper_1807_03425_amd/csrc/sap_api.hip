@@ -87,6 +87,9 @@ struct sap_ctx {
     // fused FP64 Y GEMM split over two wavefronts per 16-row tile (k_prep and
     // k_selprep run n_pad / 32 blocks; see gemm_block_deep)
     bool gemm_split = false;
+    // k_selprep: 64-row groups of Y per block (2 when there are more groups
+    // than compute units, so that one round of blocks covers the rows)
+    int gtiles = 1;
     int short_grid_it = 0;   // short-pair blocks of the iteration's pass (<= short_grid)
     int sm_grid = 0;   // fused: blocks of the soft-min tile passes
     size_t tail_lds = 0;
@@ -482,6 +485,7 @@ static sap_status init_fused(sap_ctx *h) {
     // 64-row blocks than compute units (the split doubles them)
     h->gemm_split = h->cfg.gemm == SAP_GEMM_F64 && h->vec_x && (h->n == 512 || h->n == 1024) &&
                     h->Npad / 64 < cus;
+    h->gtiles = (h->n < 512 && h->Npad / 64 > cus) ? 2 : 1;
     h->pass_grid = (int)std::max<int64_t>(
         1, std::min<int64_t>(ceil_div(2 * h->ntiles, 4), std::max<int64_t>(slots / 4, slots - h->short_grid_it)));
     // soft-min tile passes (three or four blocks per compute unit): eight
@@ -574,6 +578,7 @@ static SweepArgs<TX> sweep_args(sap_ctx *h, double *tr_min, int64_t *tr_ij, int3
     a.cap = h->cfg.cand_cap > 0 ? h->cfg.cand_cap : kCandCap;
     a.gemm = h->cfg.gemm;
     a.split = h->gemm_split ? 1 : 0;
+    a.gtiles = h->gtiles;
     return a;
 }
 
@@ -621,6 +626,13 @@ static sap_status launch_select(sap_ctx *h, int do_step, double *tr_min, int64_t
     return SAP_OK;
 }
 
+// Blocks of k_selprep: 32 rows each with the split GEMM, else 64 gtiles.
+static int64_t selprep_blocks(const sap_ctx *h) {
+    if (h->gemm_split) return h->Npad / 32;
+    const int64_t rows = 64 * (int64_t)h->gtiles;
+    return (h->Npad + rows - 1) / rows;
+}
+
 // Fused form: selection + update of iteration it and the Y GEMM of the next
 // P in one launch; the next P goes to the other buffer, which becomes the
 // current one.
@@ -628,7 +640,7 @@ template <typename TX>
 static sap_status launch_selprep(sap_ctx *h, double *tr_min, int64_t *tr_ij, int32_t *tr_cert, int it) {
     const int K = h->k;
     const SweepArgs<TX> a = sweep_args<TX>(h, tr_min, tr_ij, tr_cert, it);
-    const dim3 g0((unsigned)(h->Npad / (h->gemm_split ? 32 : 64))), blk(kPairBlock);
+    const dim3 g0((unsigned)selprep_blocks(h)), blk(kPairBlock);
     SAP_DISPATCH_K(K, SAP_TRY(launch_with(h, 6, "k_selprep", g0, blk, (uint32_t)h->tail_lds,
                                           [&](const LaunchCfg &c) {
         return KLaunch<K, TX>::selprep(c, a, h->short_grid_it, h->d_P64t_alt, h->cfg.alpha, h->cfg.rule,
@@ -654,8 +666,9 @@ static sap_status launch_iteration(sap_ctx *h, int do_step, double *tr_min, int6
 // per iteration) keep the three launches.
 template <typename TX>
 static sap_status launch_run(sap_ctx *h, int32_t iters, double *tr_min, int64_t *tr_ij, int32_t *tr_cert) {
-    const int64_t reads = (h->Npad / (h->gemm_split ? 32 : 64)) * (int64_t)(h->pass_grid + h->short_grid_it) *
-                          (int64_t)sizeof(Partial);
+    // (counted per 64-row group: where the fused launch would read more, the
+    // separate selection and GEMM launches are faster)
+    const int64_t reads = (h->Npad / 64) * (int64_t)(h->pass_grid + h->short_grid_it) * (int64_t)sizeof(Partial);
     if (h->cfg.form != SAP_FUSED || reads > (16 << 20)) {
         for (int32_t it = 0; it <= iters; ++it)
             SAP_TRY(launch_iteration<TX>(h, it < iters ? 1 : 0, tr_min, tr_ij, tr_cert, it));

@@ -284,13 +284,16 @@ __device__ __forceinline__ void gemm_block_lowp(const TX *__restrict__ X, int64_
 // earlier by k_selprep.  gemm: SAP_GEMM_F64 (below), or SAP_GEMM_F32 /
 // SAP_GEMM_BF16 (gemm_block_lowp).  With the FP64 GEMM, Y64 (if not null)
 // receives the same products unrounded (the short-pair bounds use them).
+// A block covers 64 tpw rows; this call computes the wavefront's 16 rows of
+// its tile-th group of 64.
 template <typename TX>
 __device__ __forceinline__ void gemm_block(const TX *__restrict__ X, int64_t ldx, int64_t N, int n, int k,
                            const double *__restrict__ mu, const double *__restrict__ P64t,
                            float *__restrict__ Y, double *__restrict__ Y64, int kp, int64_t Npad, bool vx,
-                           bool vp, const TX (&x0)[16], const double (&m0)[16], bool use_x0, int gemm) {
+                           bool vp, const TX (&x0)[16], const double (&m0)[16], bool use_x0, int gemm,
+                           int tpw = 1, int tile = 0) {
     const int lane = threadIdx.x & 63;
-    const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    const int64_t row0 = (((int64_t)blockIdx.x * tpw + tile) * 4 + (threadIdx.x >> 6)) * 16;
     if (row0 >= Npad) return;
     if (gemm != SAP_GEMM_F64) {
         gemm_block_lowp<TX>(X, ldx, N, n, k, mu, P64t, Y, kp, row0, vx, vp, x0, m0, use_x0, gemm);
@@ -806,6 +809,7 @@ struct SweepArgs {
     int gemm;             // arithmetic of the Y GEMM: SAP_GEMM_F64 | _F32 | _BF16
     int split;            // Y GEMM split over two wavefronts per tile (gemm_block_deep): k_prep
                           // and k_selprep then run n_pad / 32 blocks
+    int gtiles;           // k_selprep: 64-row groups of Y per block (1 or 2: the TPW instance)
 };
 
 // Candidates of a pass block.  The block keeps its running minimum key in
@@ -1916,7 +1920,7 @@ __global__ __launch_bounds__(kPairBlock) void k_select(SweepArgs<TX> a, int nsho
 // (identical inputs, identical arithmetic) into its LDS, then its rows of Y
 // from there.  Block 0 alone writes the record, the traces and P' to Pn, the
 // other P buffer: blocks still reading the current P must not see P'.
-template <int K, typename TX>
+template <int K, typename TX, int TPW>
 __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nshort, double *__restrict__ Pn,
                                                         double alpha, int rule, const double *__restrict__ mu,
                                                         float *__restrict__ Y, int64_t Npad) {
@@ -1942,7 +1946,8 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
     // the wavefront's first chunk of X and the matching means, issued
     // unconditionally (the 1/d^2 tiles serve as the spare source)
     const bool split = deep && a.split;
-    int64_t row0 = min(((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16, Npad - 16);
+    const int tpw = deep ? 1 : TPW;
+    int64_t row0 = min(((int64_t)blockIdx.x * tpw * 4 + (threadIdx.x >> 6)) * 16, Npad - 16);
     int l0 = 0;
     if (deep) {
         int cb, nch;
@@ -1992,7 +1997,13 @@ __global__ __launch_bounds__(kPairBlock) void k_selprep(SweepArgs<TX> a, int nsh
     // X rows without 16-byte loads: the first chunk is loaded now (scalar)
     if (a.n >= 64 && !pre_x) gemm_first_x_scalar<TX>(a.X, a.ldx, a.N, Npad, mu, x0, m0);
     gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, sm_sp, Y, a.Y64, a.kp, Npad, a.vx, (a.n & 1) == 0, x0, m0,
-                   a.n >= 64, a.gemm);
+                   a.n >= 64, a.gemm, tpw, 0);
+    // TPW = 2: a second group of 64 rows (more 64-row groups than compute
+    // units: one round of blocks, each taking the selection and update once
+    // for both)
+    if constexpr (TPW == 2)
+        gemm_block<TX>(a.X, a.ldx, a.N, a.n, K, mu, sm_sp, Y, a.Y64, a.kp, Npad, a.vx, (a.n & 1) == 0, x0, m0,
+                       false, a.gemm, tpw, 1);
 }
 
 #ifndef SAP_KINST   // K-independent kernels: compiled once, in the host runtime unit

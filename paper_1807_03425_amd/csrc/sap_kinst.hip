@@ -46,16 +46,21 @@ hipError_t KLaunch<K, TX>::select(const LaunchCfg &c, bool fused, const SweepArg
 template <int K, typename TX>
 hipError_t KLaunch<K, TX>::selprep(const LaunchCfg &c, const SweepArgs<TX> &a, int nshort, double *Pn,
                                    double alpha, int rule, const double *mu, float *Y, int64_t Npad) {
-    hipExtLaunchKernelGGL(k_selprep<K, TX>, c.grid, c.block, c.shmem, c.stream, c.ea, c.eb, 0, a, nshort, Pn,
-                          alpha, rule, mu, Y, Npad);
+    if (a.gtiles == 2)
+        hipExtLaunchKernelGGL(k_selprep<K, TX, 2>, c.grid, c.block, c.shmem, c.stream, c.ea, c.eb, 0, a, nshort,
+                              Pn, alpha, rule, mu, Y, Npad);
+    else
+        hipExtLaunchKernelGGL(k_selprep<K, TX, 1>, c.grid, c.block, c.shmem, c.stream, c.ea, c.eb, 0, a, nshort,
+                              Pn, alpha, rule, mu, Y, Npad);
     return hipGetLastError();
 }
 
 template <int K, typename TX>
 hipError_t KLaunch<K, TX>::set_select_lds(int bytes) {
-    const void *fns[4] = {reinterpret_cast<const void *>(&k_select<K, TX, true>),
+    const void *fns[5] = {reinterpret_cast<const void *>(&k_select<K, TX, true>),
                           reinterpret_cast<const void *>(&k_select<K, TX, false>),
-                          reinterpret_cast<const void *>(&k_selprep<K, TX>),
+                          reinterpret_cast<const void *>(&k_selprep<K, TX, 1>),
+                          reinterpret_cast<const void *>(&k_selprep<K, TX, 2>),
                           reinterpret_cast<const void *>(&k_prep<K, TX>)};
     for (const void *f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
