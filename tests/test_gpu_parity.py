@@ -150,13 +150,17 @@ def test_set_get_P_roundtrip_and_resume():
     ctx.close()
 
 
-@pytest.mark.parametrize("name,N,k", [("trig64", 300, 6), ("hyper", 300, 10), ("blob", 200, 8)])
+@pytest.mark.parametrize("name,N,k", [("trig64", 300, 6), ("hyper", 300, 10), ("blob", 200, 8),
+                                      ("hyper", 20000, 10)])
 def test_fused_run_equals_steps(name, N, k):
     """sap_run in the fused form fuses each iteration's selection and update
     with the next iteration's Y GEMM (two P buffers).  It must give exactly
     what separate sap_step calls and a final sap_min_secant give: the same
     trace and the same final basis, bit for bit.  The cases cover the
-    register update (n <= 64, k <= 8) and the block-wide LDS update."""
+    register update (n <= 64, k <= 8), the block-wide LDS update, the Y GEMM
+    split over two wavefronts per tile (blob, n = 1024) and two 64-row groups
+    per fused block (hyper at N = 20000: more row groups than compute
+    units)."""
     w = sap_inputs.make(name, N=N, k=k)
     iters = 6
     ctx_r, _ = _ctx(w, "fused")
