@@ -166,6 +166,9 @@ sap_status sap_min_secant(sap_handle h, sap_min_result *out);
  * if every product is zero, p_1 is replaced by s), modified Gram-Schmidt on
  * (P P^T s, the other basis vectors in order), and the first vector set to the
  * unit vector along (1 - alpha) P P^T s + alpha (s - P P^T s) -- in FP64.
+ * For k <= 12 (k <= 8 when n <= 64) the Gram-Schmidt step is carried out on
+ * the vectors' coordinates in the basis P, whose inner products equal the
+ * vectors' own for orthonormal P; the new vectors are P times them.
  * With out == NULL it is fully asynchronous; otherwise it synchronises and
  * reports the evaluation that drove the update. */
 sap_status sap_step(sap_handle h, sap_min_result *out_or_null);
