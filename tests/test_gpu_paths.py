@@ -368,3 +368,38 @@ def test_softmin_bwd_rejects_another_P():
         ctx.softmin_bwd(P1, 0.01, one)
     assert not torch.equal(g1, g2)
     ctx.close()
+
+
+# ------------------------------------------------------------------ graph capture
+
+def test_run_replays_from_a_captured_graph():
+    """sap_run allocates, synchronises and clears nothing, so a fused run can
+    be captured in a HIP graph.  An even number of iterations leaves the two
+    P buffers where they started, and every replay then continues the run:
+    each of three replays (with eager runs of another handle in between)
+    gives the trace of the matching eager run bit for bit."""
+    w = sap_inputs.make("trig64", N=300)
+    iters = 4
+    a = _ctx(w.X, w.P0, form="fused")
+    b = _ctx(w.X, w.P0, form="fused")
+    tr = dict(min=torch.empty(iters + 1, dtype=torch.float64, device=DEV),
+              ij=torch.empty((iters + 1, 2), dtype=torch.int64, device=DEV),
+              certified=torch.empty(iters + 1, dtype=torch.int32, device=DEV))
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        a.set_stream(s)
+        with torch.cuda.graph(g, stream=s):
+            a.run(iters, out=tr)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        ref = b.run(iters)
+        torch.cuda.synchronize()
+        assert torch.equal(tr["min"], ref["min"]), rep
+        assert torch.equal(tr["ij"], ref["ij"]), rep
+        assert torch.equal(tr["certified"], ref["certified"]) and bool((ref["certified"] == 1).all()), rep
+    assert np.array_equal(a.get_P().cpu().numpy(), b.get_P().cpu().numpy())
+    a.close()
+    b.close()
