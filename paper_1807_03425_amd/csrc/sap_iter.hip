@@ -737,17 +737,21 @@ __device__ __forceinline__ uint32_t wave_min_u32_fast(uint32_t v) {
 // four wavefront results in the same order, so the whole block holds the
 // same value with one barrier.  All 256 threads must call it; sync_after
 // adds the barrier a later call needs before it may reuse the staging slots.
+// wave_uniform: every lane already holds its wavefront's values (lane 0's
+// stand for the wavefront), so the wavefront reductions are skipped.
 __device__ Partial block_reduce_partial(double r, int32_t i, int32_t j, double r2, int32_t nres, int32_t ntl,
                                         int32_t nviol, uint32_t kmin, uint32_t limit, Partial *out,
-                                        bool sync_after) {
+                                        bool sync_after, bool wave_uniform = false) {
     __shared__ Partial sb[kPairBlock / kWave];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    wave_min_lex2_fast(r, i, j, r2);
-    nres = wave_sum_i32_fast(nres);
-    ntl = wave_sum_i32_fast(ntl);
-    nviol = wave_sum_i32_fast(nviol);
-    kmin = wave_min_u32_fast(kmin);
-    limit = wave_min_u32_fast(limit);
+    if (!wave_uniform) {
+        wave_min_lex2_fast(r, i, j, r2);
+        nres = wave_sum_i32_fast(nres);
+        ntl = wave_sum_i32_fast(ntl);
+        nviol = wave_sum_i32_fast(nviol);
+        kmin = wave_min_u32_fast(kmin);
+        limit = wave_min_u32_fast(limit);
+    }
     if (lane == 0) sb[wv] = Partial{r, r2, i, j, nres, ntl, nviol, kmin, limit, 0};
     __syncthreads();
     Partial b = sb[0];
@@ -1031,8 +1035,10 @@ __device__ __forceinline__ void finish_pass_block(const SweepArgs<TX> &a, const 
         }
     }
     wb.nviol += cl.lost;   // dropped candidates: the result is not certified
-    block_reduce_partial(wb.r, wb.i, wb.j, wb.r2, lane == 0 ? wb.nwin : 0, lane == 0 ? wb.nunits : 0,
-                         lane == 0 ? wb.nviol : 0, kmin, cl.limit, out, false);
+    // every lane holds the wavefront's values: the rescoring's r is the same
+    // in every lane (exact_r_wave), and the counters, kmin and the limit are
+    // wavefront-uniform
+    block_reduce_partial(wb.r, wb.i, wb.j, wb.r2, wb.nwin, wb.nunits, wb.nviol, kmin, cl.limit, out, false, true);
 }
 
 // Fused pass block pb.  Wavefront w = 4 pb + slot takes work items
