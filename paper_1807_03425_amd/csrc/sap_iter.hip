@@ -90,6 +90,56 @@ __device__ __forceinline__ void wave_sum_many(double (&v)[NV], int from = 0) {
     for (int a = 0; a < NV; ++a) if (a >= from) v[a] = pair_sum32(v[a]);
 }
 
+// mine + (other of lane ^ 2^S), S < 4: quad xor 1, quad xor 2, xor 4 as a
+// quad reversal followed by the half-row mirror (lane L reads lane L ^ 4),
+// xor 8 as the 16-lane rotation by 8.  The partners are those of
+// wave_sum_fast's steps (aligned lane groups of 2, 4, 8, 16), so a sum built
+// from these steps and the permlane swaps has wave_sum_fast's bits.
+template <int S>
+__device__ __forceinline__ double xchg_add(double mine, double other) {
+    if constexpr (S == 0) return mine + dpp_f64<0xB1>(other);
+    else if constexpr (S == 1) return mine + dpp_f64<0x4E>(other);
+    else if constexpr (S == 2) return mine + dpp_f64<0x141>(dpp_f64<0x1B>(other));
+    else return mine + dpp_f64<0x128>(other);
+}
+
+// Wavefront sums of v[0..NV-1] (NV <= 16), transposed: the exchange at
+// distance 2^s (s < H = ceil(log2 NV)) halves the values each lane carries
+// -- the lane keeps the half whose index has bit s equal to its lane's bit
+// s and receives its partner's share of that half -- and the later
+// exchanges add whole sums.  Lane L ends with the total of index L mod 2^H,
+// with the bits wave_sum_fast gives that index: about a quarter of the
+// exchanges of NV separate reductions.
+template <int NV>
+__device__ __forceinline__ double wave_sum_transposed(const double (&v)[NV]) {
+    static_assert(NV >= 1 && NV <= 16, "reduction batch");
+    constexpr int H = NV <= 1 ? 0 : NV <= 2 ? 1 : NV <= 4 ? 2 : NV <= 8 ? 3 : 4;
+    const int lane = threadIdx.x & (kWave - 1);
+    double c[1 << H];
+#pragma unroll
+    for (int e = 0; e < (1 << H); ++e) c[e] = e < NV ? v[e] : 0.0;
+#pragma unroll
+    for (int st = 0; st < H; ++st) {
+        const bool up = (lane >> st) & 1;
+#pragma unroll
+        for (int u = 0; u < (1 << (H - 1 - st)); ++u) {
+            const double lo = c[2 * u], hi = c[2 * u + 1];
+            const double mine = up ? hi : lo, other = up ? lo : hi;
+            if (st == 0) c[u] = xchg_add<0>(mine, other);
+            else if (st == 1) c[u] = xchg_add<1>(mine, other);
+            else if (st == 2) c[u] = xchg_add<2>(mine, other);
+            else c[u] = xchg_add<3>(mine, other);
+        }
+    }
+    double t = c[0];
+    if constexpr (H <= 0) t = xchg_add<0>(t, t);
+    if constexpr (H <= 1) t = xchg_add<1>(t, t);
+    if constexpr (H <= 2) t = xchg_add<2>(t, t);
+    if constexpr (H <= 3) t = xchg_add<3>(t, t);
+    t = pair_sum16(t);
+    return pair_sum32(t);
+}
+
 // ------------------------------------------------------------------ GEMM
 
 // 16 consecutive elements p[0..15] as FP64 (exact for FP32): 16-byte vector
@@ -599,7 +649,16 @@ __device__ __forceinline__ double exact_r_wave(const TX *__restrict__ X, int64_t
             for (int q = 0; q < K; ++q) v[q] = __builtin_fma(p[u][q], dl, v[q]);
         }
     }
-    wave_sum_many<K + 1>(v);
+    if constexpr (K + 1 <= 16) {
+        // lane q holds the total of v[q]; read lanes 0..K back (uniform)
+        const double t = wave_sum_transposed<K + 1>(v);
+        const int tl = __double2loint(t), th = __double2hiint(t);
+#pragma unroll
+        for (int q = 0; q <= K; ++q)
+            v[q] = __hiloint2double(__builtin_amdgcn_readlane(th, q), __builtin_amdgcn_readlane(tl, q));
+    } else {
+        wave_sum_many<K + 1>(v);
+    }
     double r2 = 0.0;
 #pragma unroll
     for (int q = 0; q < K; ++q) r2 = __builtin_fma(v[q], v[q], r2);
@@ -1540,53 +1599,6 @@ __device__ __forceinline__ void coord_mgs(const double (&c)[K], int t, double (&
             for (int r = 0; r < K; ++r) G[jv][r] = G[jv][r] - d * G[mm][r];
         }
     }
-}
-
-// v + (v of the exchange partner at distance 2^S inside the wavefront):
-// quad xor 1, quad xor 2, 16-lane rotation by 4 (the partner differs in bit
-// 2 and agrees below it), rotation by 8 (xor 8), then the permlane swaps.
-template <int S>
-__device__ __forceinline__ double xchg_add(double mine, double other) {
-    if constexpr (S == 0) return mine + dpp_f64<0xB1>(other);
-    else if constexpr (S == 1) return mine + dpp_f64<0x4E>(other);
-    else if constexpr (S == 2) return mine + dpp_f64<0x124>(other);
-    else return mine + dpp_f64<0x128>(other);
-}
-
-// Wavefront sums of v[0..NV-1] (NV <= 16), transposed: the exchange at
-// distance 2^s (s < H = ceil(log2 NV)) halves the values each lane carries
-// -- the lane keeps the half whose index has bit s equal to its lane's bit
-// s and receives its partner's share of that half -- and the later
-// exchanges add whole sums.  Lane L ends with the total of index L mod 2^H:
-// about a quarter of the exchanges of NV separate reductions.
-template <int NV>
-__device__ __forceinline__ double wave_sum_transposed(const double (&v)[NV]) {
-    static_assert(NV >= 1 && NV <= 16, "reduction batch");
-    constexpr int H = NV <= 1 ? 0 : NV <= 2 ? 1 : NV <= 4 ? 2 : NV <= 8 ? 3 : 4;
-    const int lane = threadIdx.x & (kWave - 1);
-    double c[1 << H];
-#pragma unroll
-    for (int e = 0; e < (1 << H); ++e) c[e] = e < NV ? v[e] : 0.0;
-#pragma unroll
-    for (int st = 0; st < H; ++st) {
-        const bool up = (lane >> st) & 1;
-#pragma unroll
-        for (int u = 0; u < (1 << (H - 1 - st)); ++u) {
-            const double lo = c[2 * u], hi = c[2 * u + 1];
-            const double mine = up ? hi : lo, other = up ? lo : hi;
-            if (st == 0) c[u] = xchg_add<0>(mine, other);
-            else if (st == 1) c[u] = xchg_add<1>(mine, other);
-            else if (st == 2) c[u] = xchg_add<2>(mine, other);
-            else c[u] = xchg_add<3>(mine, other);
-        }
-    }
-    double t = c[0];
-    if constexpr (H <= 0) t = xchg_add<0>(t, t);
-    if constexpr (H <= 1) t = xchg_add<1>(t, t);
-    if constexpr (H <= 2) t = xchg_add<2>(t, t);
-    if constexpr (H <= 3) t = xchg_add<3>(t, t);
-    t = pair_sum16(t);
-    return pair_sum32(t);
 }
 
 // v[0..NV-1] summed over the block, the same bits in every thread:
