@@ -665,6 +665,66 @@ __device__ __forceinline__ double exact_r_wave(const TX *__restrict__ X, int64_t
     return sqrt(r2) / sqrt(v[K]);
 }
 
+// exact_r_wave for two pairs at once (i1, j1) and (i2, j2): each group's
+// loads of P serve both pairs, both pairs' rows are in flight together, and
+// one transposed wavefront sum reduces the 2(K + 1) partial sums.  Each
+// pair's partial sums are formed exactly as in exact_r_wave, so *r1 and *r2
+// carry its bits.
+template <int K, typename TX, int U = (K <= 8 ? 4 : 2)>
+__device__ __forceinline__ void exact_r_wave2(const TX *__restrict__ X, int64_t ldx, int n, const double *P64t,
+                                              int64_t i1, int64_t j1, int64_t i2, int64_t j2, double *r1,
+                                              double *r2) {
+    static_assert(2 * (K + 1) <= 16, "one transposed sum");
+    const int lane = threadIdx.x & 63;
+    const TX *xi1 = X + i1 * ldx, *xj1 = X + j1 * ldx;
+    const TX *xi2 = X + i2 * ldx, *xj2 = X + j2 * ldx;
+    double v[2 * (K + 1)];
+#pragma unroll
+    for (int q = 0; q < 2 * (K + 1); ++q) v[q] = 0.0;
+#pragma unroll 1
+    for (int base = 0; base < n; base += U * kWave) {
+        const int l0 = base + lane;
+        double a1[U], b1[U], a2[U], b2[U], p[U][K];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int lc = min(l0 + u * kWave, n - 1);
+            a1[u] = (double)xi1[lc];
+            b1[u] = (double)xj1[lc];
+            a2[u] = (double)xi2[lc];
+            b2[u] = (double)xj2[lc];
+#pragma unroll
+            for (int q = 0; q < K; ++q) p[u][q] = P64t[(int64_t)q * n + lc];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool in = l0 + u * kWave < n;
+            const double d1 = in ? a1[u] - b1[u] : 0.0;
+            const double d2 = in ? a2[u] - b2[u] : 0.0;
+            v[K] = __builtin_fma(d1, d1, v[K]);
+            v[2 * K + 1] = __builtin_fma(d2, d2, v[2 * K + 1]);
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                v[q] = __builtin_fma(p[u][q], d1, v[q]);
+                v[K + 1 + q] = __builtin_fma(p[u][q], d2, v[K + 1 + q]);
+            }
+        }
+    }
+    // lane e holds the total of v[e]; read both pairs' sums back (uniform)
+    const double t = wave_sum_transposed<2 * (K + 1)>(v);
+    const int tl = __double2loint(t), th = __double2hiint(t);
+#pragma unroll
+    for (int e = 0; e < 2 * (K + 1); ++e)
+        v[e] = __hiloint2double(__builtin_amdgcn_readlane(th, e), __builtin_amdgcn_readlane(tl, e));
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        s1 = __builtin_fma(v[q], v[q], s1);
+        s2 = __builtin_fma(v[K + 1 + q], v[K + 1 + q], s2);
+    }
+    *r1 = sqrt(s1) / sqrt(v[K]);
+    *r2 = sqrt(s2) / sqrt(v[2 * K + 1]);
+}
+
 // Squared-ratio threshold of the rescoring window.  With coarse values
 // obeying |r~ - r| <= e_abs + e_rel r, any pair whose true r does not exceed
 // the true r of the coarse argmin has r~ <= T; T^2 is rounded up to FP32.
@@ -1043,6 +1103,44 @@ __device__ __forceinline__ uint32_t block_run_min(uint32_t *s_run, uint32_t m) {
     return old < m ? old : m;
 }
 
+// Fold the FP64 r of window pair ij (coarse key kv) into the wavefront's
+// best, second-smallest value and counters.
+template <typename TX>
+__device__ __forceinline__ void take_window_pair(const SweepArgs<TX> &a, double r, int2 ij, uint32_t kv,
+                                                 WaveBest &wb) {
+    ++wb.nwin;
+    wb.nviol += bound_broken(r, (double)__uint_as_float(kv), a.e_abs, a.e_rel);
+    if (lex_less(r, ij.x, ij.y, wb.r, wb.i, wb.j)) {
+        wb.r2 = wb.r;
+        wb.r = r; wb.i = ij.x; wb.j = ij.y;
+    } else {
+        wb.r2 = fmin(wb.r2, r);
+    }
+}
+
+// The first candidate at or after g, stepping by four over the four lists
+// taken together (lengths n0, n1, n2, then the rest of tot), whose key lies
+// in the window T2b: its key and pair, and g at it; false when none is left.
+__device__ __forceinline__ bool next_window_entry(int &g, int tot, int n0, int n1, int n2,
+                                                  const int2 (*cij)[kCandCap], const uint32_t (*ckey)[kCandCap],
+                                                  uint32_t T2b, uint32_t &kv, int2 &ij) {
+#pragma unroll 1
+    for (; g < tot; g += kPairBlock / kWave) {
+        int L = 0, c = g;   // (list, entry) of the g-th candidate (wavefront-uniform)
+        if (c >= n0) {
+            c -= n0; L = 1;
+            if (c >= n1) {
+                c -= n1; L = 2;
+                if (c >= n2) { c -= n2; L = 3; }
+            }
+        }
+        kv = ckey[L][c];
+        ij = cij[L][c];
+        if (kv <= T2b) return true;
+    }
+    return false;
+}
+
 // After every wavefront's sweep: the block's final minimum, then the four
 // wavefronts share the rescoring of the block's candidates inside its window
 // (every fourth entry of the four lists taken together, so that one long
@@ -1065,31 +1163,42 @@ __device__ __forceinline__ void finish_pass_block(const SweepArgs<TX> &a, const 
         const uint32_t T2b = item_window(run, a.wa, a.wb);
         const int n0 = s_cn[0], n1 = s_cn[1], n2 = s_cn[2], n3 = s_cn[3];
         const int tot = n0 + n1 + n2 + n3;
+        int g = wv;
+        uint32_t k1, k2;
+        int2 p1, p2;
+        bool paired = false;
+        if constexpr (K <= 4) {
+            // several component groups (n > 64): the wavefront's window
+            // entries two at a time, the second pair's rows in flight with
+            // the first's (the order of the folds does not change the result)
+            if (a.n > kWave) {
+                paired = true;
 #pragma unroll 1
-        for (int g = wv; g < tot; g += kPairBlock / kWave) {
-            int L = 0, c = g;   // (list, entry) of the g-th candidate (wavefront-uniform)
-            if (c >= n0) {
-                c -= n0; L = 1;
-                if (c >= n1) {
-                    c -= n1; L = 2;
-                    if (c >= n2) { c -= n2; L = 3; }
+                while (next_window_entry(g, tot, n0, n1, n2, cij, ckey, T2b, k1, p1)) {
+                    g += kPairBlock / kWave;
+                    if (next_window_entry(g, tot, n0, n1, n2, cij, ckey, T2b, k2, p2)) {
+                        g += kPairBlock / kWave;
+                        double r1, r2;
+                        exact_r_wave2<K, TX>(a.X, a.ldx, a.n, a.P64t, p1.x, p1.y, p2.x, p2.y, &r1, &r2);
+                        take_window_pair(a, r1, p1, k1, wb);
+                        take_window_pair(a, r2, p2, k2, wb);
+                    } else {
+                        take_window_pair(a, exact_r_wave<K, TX>(a.X, a.ldx, a.n, a.P64t, p1.x, p1.y), p1, k1, wb);
+                    }
                 }
             }
-            const uint32_t kv = ckey[L][c];
-            if (kv > T2b) continue;
-            const int2 ij = cij[L][c];
-            double r;
-            // one group of components when n <= 64 (no clamped extra loads;
-            // K <= 7, where the second instance fits the register budget)
-            if (K <= 7 && a.n <= kWave) r = exact_r_wave<K, TX, 1>(a.X, a.ldx, a.n, a.P64t, ij.x, ij.y);
-            else r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, a.P64t, ij.x, ij.y);
-            ++wb.nwin;
-            wb.nviol += bound_broken(r, (double)__uint_as_float(kv), a.e_abs, a.e_rel);
-            if (lex_less(r, ij.x, ij.y, wb.r, wb.i, wb.j)) {
-                wb.r2 = wb.r;
-                wb.r = r; wb.i = ij.x; wb.j = ij.y;
-            } else {
-                wb.r2 = fmin(wb.r2, r);
+        }
+        if (!paired) {
+#pragma unroll 1
+            while (next_window_entry(g, tot, n0, n1, n2, cij, ckey, T2b, k1, p1)) {
+                g += kPairBlock / kWave;
+                double r;
+                // one group of components when n <= 64 (no clamped extra
+                // loads; K <= 7, where the second instance fits the register
+                // budget)
+                if (K <= 7 && a.n <= kWave) r = exact_r_wave<K, TX, 1>(a.X, a.ldx, a.n, a.P64t, p1.x, p1.y);
+                else r = exact_r_wave<K, TX>(a.X, a.ldx, a.n, a.P64t, p1.x, p1.y);
+                take_window_pair(a, r, p1, k1, wb);
             }
         }
     }
